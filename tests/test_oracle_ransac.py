@@ -1,0 +1,122 @@
+"""Pins for the oracle's RANSAC reference (CPU only)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import homography as hg
+from oracle import ransac
+from oracle.sampling import sample_indices
+
+
+def tiny_set(seed, n=8, n_in=5):
+    rng = np.random.default_rng(seed)
+    x1 = rng.uniform(0, 100, n)
+    y1 = rng.uniform(0, 100, n)
+    H = np.array([[0.9, -0.2, 5.0], [0.25, 1.1, -3.0], [1e-3, -5e-4, 1.0]])
+    w = H[2, 0] * x1 + H[2, 1] * y1 + H[2, 2]
+    x2 = (H[0, 0] * x1 + H[0, 1] * y1 + H[0, 2]) / w + rng.normal(0, 0.3, n)
+    y2 = (H[1, 0] * x1 + H[1, 1] * y1 + H[1, 2]) / w + rng.normal(0, 0.3, n)
+    x2[n_in:] = rng.uniform(0, 100, n - n_in)
+    y2[n_in:] = rng.uniform(0, 100, n - n_in)
+    return np.stack([x1, y1, x2, y2]).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_counts_match_brute_force(seed):
+    corr = tiny_set(seed)
+    tau = 2.0
+    brute = ransac.brute_force_counts(corr, tau)
+    ref = ransac.ransac_ref(corr, 3000, tau, seed=seed)
+    seen = set()
+    for j in range(3000):
+        sub = tuple(sorted(ref["idx"][:, j].tolist()))
+        seen.add(sub)
+        if not ref["valid"][j]:
+            continue
+        assert ref["count_lo"][j] <= brute[sub] <= ref["count_hi"][j]
+    assert len(seen) == 70                 # every 4-subset of 8 was drawn
+    valid_subs = {tuple(sorted(ref["idx"][:, j].tolist())) for j in range(3000) if ref["valid"][j]}
+    assert ref["best_count"] == max(brute[s] for s in valid_subs)
+    # the best H's mask is its inlier set
+    d = ransac.transfer_error(ref["best_H"][None], corr)[0]
+    assert np.array_equal(ref["mask"], (d <= tau).astype(np.uint8))
+    assert ref["mask"].sum() == ref["best_count"]
+
+
+def test_ties_go_to_lowest_index():
+    rng = np.random.default_rng(4)
+    x1 = rng.integers(0, 600, 50).astype(np.float32)
+    y1 = rng.integers(0, 400, 50).astype(np.float32)
+    corr = np.stack([x1, y1, x1 + 10, y1 - 7])
+    ref = ransac.ransac_ref(corr, 64, 3.0, seed=9)
+    assert ref["counts"][ref["valid"]].min() == 50      # every valid sample explains all
+    assert ref["best_hyp"] == int(np.argmax(ref["valid"]))
+
+
+def test_all_degenerate():
+    corr = np.ones((4, 30), np.float32)
+    ref = ransac.ransac_ref(corr, 32, 3.0, seed=1)
+    assert not ref["valid"].any()
+    assert ref["best_hyp"] == -1 and ref["best_count"] == 0
+    assert not ref["mask"].any() and not ref["best_H"].any()
+
+
+def test_hypothesis_h_is_aca_of_sample():
+    cs = synth.config2()
+    idx, H32, flags, valid = ransac.hypotheses(cs.corr, 64, seed=2)
+    assert np.array_equal(idx, sample_indices(2000, 64, 2))
+    for j in range(0, 64, 9):
+        src = np.array([cs.corr[c, idx[k, j]] for k in range(4) for c in (0, 1)])
+        dst = np.array([cs.corr[c, idx[k, j]] for k in range(4) for c in (2, 3)])
+        Hx = hg.exact_h(src, dst)
+        assert hg.herr(H32[j], Hx) < 1e-6
+
+
+def _fp32_division_free(H, corr, tau, fused):
+    """float32 evaluation of ru^2 + rv^2 <= tau^2 w^2 (emulation, test only)."""
+    H = H.astype(np.float32)
+    x1, y1, x2, y2 = (c.astype(np.float32)[None] for c in corr)
+    f32 = np.float32
+
+    def fma(a, b, c):
+        if fused:   # product exact in float64, sum rounded there, then to float32
+            return (a.astype(np.float64) * b + c).astype(f32)
+        return (a * b + c).astype(f32)
+
+    def row(i):
+        return fma(H[:, i, 0, None], x1, fma(H[:, i, 1, None], y1, H[:, i, 2, None]))
+
+    u, v, w = row(0), row(1), row(2)
+    ru = fma(-x2, w, u)
+    rv = fma(-y2, w, v)
+    d = fma(rv, rv, ru * ru)
+    tw = f32(tau) * w
+    return d <= tw * tw
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_decision_band_covers_float32_evaluation(fused):
+    cs = synth.config2()
+    idx, H32, flags, valid = ransac.hypotheses(cs.corr, 4096, seed=2)
+    tau = 3.0
+    n_mis = n_band = 0
+    for a in range(0, 4096, 512):
+        H = H32[a:a + 512][valid[a:a + 512]]
+        d = ransac.transfer_error(H, cs.corr)
+        band = ransac.decision_band(H, cs.corr, tau)
+        got = _fp32_division_free(H, cs.corr, tau, fused)
+        mis = got != (d <= tau)
+        n_mis += mis.sum()
+        assert np.all(np.abs(d - tau)[mis] <= band[mis])
+        n_band += (np.abs(d - tau) <= np.maximum(band, 1e-4)).sum()
+    # the band is narrow: a handful of the 8.2M (hypothesis, point) pairs
+    assert n_band < 100
+
+
+def test_config2_planted_model_found():
+    cs = synth.config2()
+    ref = ransac.ransac_ref(cs.corr, 4096, 3.0, seed=2)
+    assert ref["best_count"] > 350
+    recall = (ref["mask"].astype(bool) & cs.inlier).sum() / cs.inlier.sum()
+    assert recall > 0.6
+    assert ref["count_lo"].sum() <= ref["counts"].sum() <= ref["count_hi"].sum()

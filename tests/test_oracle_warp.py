@@ -1,0 +1,100 @@
+"""Pins for the oracle's 4-point-offset pipeline (CPU only, torch float64)."""
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+import synth
+from oracle import homography as hg
+from oracle import warp
+
+
+@pytest.fixture(scope="module")
+def small():
+    pb = synth.patches(6, 11, size=32, sigma=2.0, max_shift=4, max_offset=6.0)
+    return pb
+
+
+def test_bilinear_matches_scipy(small):
+    img = torch.as_tensor(small.img, dtype=torch.float64)
+    rng = np.random.default_rng(0)
+    sx = torch.as_tensor(rng.uniform(-3, 35, (6, 500)))
+    sy = torch.as_tensor(rng.uniform(-3, 35, (6, 500)))
+    got = warp.bilinear_zero(img, sx, sy).numpy()
+    for b in range(6):
+        ref = ndimage.map_coordinates(small.img[b].astype(np.float64), [sy[b].numpy(), sx[b].numpy()],
+                                      order=1, mode="grid-constant", cval=0.0)
+        assert np.abs(got[b] - ref).max() < 1e-12
+
+
+def test_zero_offsets_identity(small):
+    img = torch.as_tensor(small.img, dtype=torch.float64)
+    H = warp.h_dlt(torch.zeros(6, 4, 2, dtype=torch.float64), 32)
+    assert torch.allclose(H, torch.eye(3, dtype=torch.float64).expand(6, 3, 3), atol=1e-12)
+    Iw = warp.warp(img, H)
+    assert torch.abs(Iw - img).max() < 1e-9
+
+
+def test_integer_translation_shifts(small):
+    img = torch.as_tensor(small.img, dtype=torch.float64)
+    off = torch.zeros(6, 4, 2, dtype=torch.float64)
+    off[:, :, 0] = 3.0
+    off[:, :, 1] = -2.0
+    Iw = warp.warp(img, warp.h_dlt(off, 32)).numpy()
+    ref = np.zeros_like(small.img, dtype=np.float64)
+    # I_w(x, y) = I(x - 3, y + 2)
+    ref[:, 0:30, 3:32] = small.img[:, 2:32, 0:29]
+    assert np.abs(Iw - ref).max() < 1e-9
+
+
+def test_rect_solver_matches_dlt():
+    rng = np.random.default_rng(1)
+    off = torch.as_tensor(rng.uniform(-32, 32, (50, 4, 2)))
+    assert hg.herr(warp.h_rect(off, 128).numpy(), warp.h_dlt(off, 128).numpy()).max() < 1e-12
+
+
+def test_rect_jacobian_finite_differences():
+    rng = np.random.default_rng(2)
+    off = torch.as_tensor(rng.uniform(-32, 32, (4, 4, 2)), dtype=torch.float64).requires_grad_(True)
+    gH = torch.as_tensor(rng.normal(size=(4, 3, 3)))
+    (g,) = torch.autograd.grad((warp.h_rect(off, 128) * gH).sum(), off)
+    h = 1e-5
+    fd = torch.zeros_like(g)
+    with torch.no_grad():
+        for k in range(4):
+            for c in range(2):
+                e = torch.zeros_like(off)
+                e[:, k, c] = h
+                fd[:, k, c] = ((warp.h_rect(off + e, 128) - warp.h_rect(off - e, 128)) * gH).sum((1, 2)) / (2 * h)
+    assert torch.allclose(g, fd, rtol=1e-7, atol=1e-6 * g.abs().max().item())
+
+
+def test_loss_gradient_finite_differences(small):
+    off = torch.as_tensor(small.offsets, dtype=torch.float64)
+    L, g = warp.loss_and_grad(off, small.img, small.tgt)
+    fd = warp.loss_fd_grad(off, small.img, small.tgt, h=1e-6)
+    rel = (g - fd).norm(dim=(1, 2)) / g.norm(dim=(1, 2))
+    assert rel.max() < 1e-4
+    # the solver choice does not change the loss (H only matters up to scale)
+    L2, g2 = warp.loss_and_grad(off, small.img, small.tgt, solver=warp.h_rect)
+    assert torch.allclose(L, L2, rtol=1e-12)
+    assert torch.allclose(g, g2, rtol=1e-8, atol=1e-12)
+
+
+def test_loss_zero_at_true_shift():
+    # the target is the source displaced by an integer shift: offsets equal to
+    # minus that shift align them everywhere both are defined
+    pb = synth.patches(3, 5, size=32, sigma=2.0, max_shift=3)
+    off = np.zeros((3, 4, 2))
+    off[:, :, 0] = -pb.shift[:, 0, None]
+    off[:, :, 1] = -pb.shift[:, 1, None]
+    H = warp.h_dlt(torch.as_tensor(off), 32)
+    Iw = warp.warp(torch.as_tensor(pb.img, dtype=torch.float64), H).numpy()
+    # in the overlap, I_w equals T up to the independent standardisation of each crop
+    for b in range(3):
+        sx, sy = pb.shift[b]
+        ys = slice(max(0, -sy), 32 - max(0, sy))
+        xs = slice(max(0, -sx), 32 - max(0, sx))
+        a = Iw[b][ys, xs].ravel()
+        t = pb.tgt[b][ys, xs].ravel().astype(np.float64)
+        assert np.corrcoef(a, t)[0, 1] > 0.999999

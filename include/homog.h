@@ -1,0 +1,195 @@
+/*
+ * homog.h -- C ABI of libhomog, an MI355X (gfx950) implementation of the
+ * minimal 4-point homography solvers of Cai et al., "Fast and Interpretable 2D
+ * Homography Decomposition: Similarity-Kernel-Similarity and
+ * Affine-Core-Affine Transformations" (arXiv 2402.18008), the RANSAC scoring
+ * that consumes them and a differentiable 4-point-offset pipeline.
+ *
+ * Conventions shared by every call
+ *  - Every array pointer is a DEVICE pointer owned by the caller unless stated
+ *    otherwise; the library never frees or keeps one (a graph keeps the
+ *    pointers it captured until hg_graph_destroy).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ *  - Arguments are validated on the host before any HIP call; invalid ones
+ *    return HG_EINVAL and launch nothing. A HIP failure returns HG_EHIP.
+ *    hg_last_error() gives the detail of the last failing call of the calling
+ *    thread. No C++ exception crosses this interface.
+ *  - Degenerate inputs are not errors: they are reported through flags (solver)
+ *    or by excluding the hypothesis (RANSAC).
+ *  - Point order of a 4-point problem: M, N, P, Q. In the ACA decomposition
+ *    (Sec. 4) M, N, P are the three anchor points and Q the fourth point; in
+ *    SKS (Sec. 3) M, N are the two anchor points.
+ *  - H is 3x3 row-major up to scale: h11 h12 h13 h21 h22 h23 h31 h32 h33.
+ */
+#ifndef HOMOG_H
+#define HOMOG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------ */
+enum {
+  HG_OK = 0,
+  HG_EINVAL = -1,       /* invalid argument (host-side check)            */
+  HG_EHIP = -2,         /* a HIP runtime call failed                     */
+  HG_EWORKSPACE = -3,   /* workspace missing or smaller than required    */
+  HG_EUNSUPPORTED = -4  /* valid request the library does not implement  */
+};
+
+/* Static text for a status code. */
+const char *hg_status_str(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *hg_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int hg_version(void);
+
+/* ---- batched 4-point solver ---------------------------------------------
+ * Solves n independent 4-point problems x2_i ~ H x1_i (i = M, N, P, Q): the
+ * minimal homography problem of Sec. 2.1.
+ *   method  HG_ACA: affine-core-affine, H = H_A2^-1 H_C H_A1 (Sec. 4,
+ *                   eq. ACA, the division-free core of eqs. H_C_2 / C_11);
+ *           HG_SKS: similarity-kernel-similarity, H = H_S2^-1 H_K H_S1
+ *                   (Sec. 3, eq. HS).
+ *   src, dst  8 planes each of n floats, plane k at offset k*ld:
+ *             x_M y_M x_N y_N x_P y_P x_Q y_Q (source resp. target points).
+ *   ld        plane stride in elements, ld >= n.
+ *   H         9 planes of n floats at stride ld (output): the solution scaled
+ *             by the power of two that brings max|h_ij| into [0.5, 1), then
+ *             rounded to float (arithmetic inside is double precision).
+ *   flags     n bytes (output, may be NULL): bit0 = near-degenerate (one of the
+ *             8 triangles of either side has minimum height <= 1e-2 px);
+ *             bit1 = non-finite input; bit2 = H was zero or non-finite and
+ *             has been written as zeros.
+ * Fast path when src, dst, H are 16-byte aligned, flags 4-byte aligned and
+ * ld % 4 == 0; any other layout is accepted and takes a scalar path.
+ * n == 0 is a no-op. Errors: NULL pointer (other than flags), n < 0, ld < n,
+ * unknown method -> HG_EINVAL.                                               */
+enum { HG_ACA = 0, HG_SKS = 1 };
+enum { HG_FLAG_NEAR_DEGENERATE = 1, HG_FLAG_NONFINITE_INPUT = 2, HG_FLAG_ZERO_H = 4 };
+int hg_solve4(int method, const float *src, const float *dst, int64_t n, int64_t ld,
+              float *H, uint8_t *flags, void *stream);
+
+/* ---- single-pair RANSAC --------------------------------------------------
+ * Hypothesise and verify (RANSAC stage of the experiments): hypothesis j
+ * draws 4 distinct correspondences with Philox4x32-10 (key = seed, counter =
+ * (j, 0, 0, 0)) and Floyd's algorithm, solves ACA on them (as hg_solve4) and
+ * counts the points with one-way transfer error ||pi(H x1) - x2|| <= thresh
+ * (evaluated division-free in float). Degenerate samples (any flag bit) are
+ * skipped. best = largest count, ties to the lowest j.
+ *   corr        4 planes x1 y1 x2 y2 of n_pts floats at stride ld (>= n_pts).
+ *   n_pts >= 4, n_hyp >= 1, thresh finite and > 0.
+ *   best_H      9 floats (output); zeros if no hypothesis is valid.
+ *   best_count, best_hyp  1 int32 each (output); best_hyp = -1 if none valid.
+ *   inlier_mask n_pts bytes (output): 1 for inliers of best_H.
+ *   hyp_counts  n_hyp int32 (output, may be NULL): per-hypothesis counts,
+ *               0 for degenerate samples.
+ *   ws          device workspace of at least hg_ransac_ws_bytes(...) bytes.
+ * hg_ransac is the fused form (sampling, solving and scoring in one kernel,
+ * then a mask kernel); hg_ransac_plain runs the same arithmetic as separate
+ * kernels (solve all -> H buffer, score, argmax, mask) and returns identical
+ * results.                                                                    */
+size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp);
+int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,
+              uint64_t seed, float *best_H, int32_t *best_count, int32_t *best_hyp,
+              uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, size_t ws_bytes,
+              void *stream);
+int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,
+                    uint64_t seed, float *best_H, int32_t *best_count, int32_t *best_hyp,
+                    uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* ---- batched RANSAC over many uneven pairs --------------------------------
+ * Pair p owns points [off[p], off[p+1]) of the concatenated planes (corr at
+ * stride ld >= off[n_pairs]); every pair runs n_hyp hypotheses with Philox
+ * counter (j, p, 0, 0). One persistent kernel drains a queue of (pair,
+ * hypothesis block) items, largest pairs first; the last block to finish a
+ * pair writes its mask. Results equal hg_ransac on each pair with counter
+ * word 1 = p.
+ *   off         n_pairs + 1 int64 (device); every pair needs >= 4 points.
+ *   best_H      n_pairs x 9 floats; best_count, best_hyp n_pairs int32;
+ *   inlier_mask off[n_pairs] bytes; hyp_counts n_pairs x n_hyp or NULL.
+ *   tune        launch shape, NULL = the cached autotuned or default choice.
+ *   ws          >= hg_ransac_batched_ws_bytes(n_pairs, n_hyp) bytes.       */
+typedef struct {
+  int32_t pts_per_lane;    /* points held in registers per lane: 4 or 8     */
+  int32_t hyps_per_block;  /* hypotheses per work item: 16, 32 or 64         */
+  int32_t blocks_per_cu;   /* persistent blocks per compute unit: 1..8       */
+  int32_t reserved;        /* 0                                              */
+} hg_ransac_tuning;
+
+size_t hg_ransac_batched_ws_bytes(int32_t n_pairs, int32_t n_hyp);
+int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
+                      int32_t n_hyp, float thresh, uint64_t seed, const hg_ransac_tuning *tune,
+                      float *best_H, int32_t *best_count, int32_t *best_hyp,
+                      uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* Times every supported tuning on the given problem (allocates temporary
+ * outputs, synchronises the stream) and stores the fastest in *out and in the
+ * process-wide cache used when tune == NULL; also written to the JSON file
+ * named by HG_AUTOTUNE_CACHE if that variable is set. off_host mirrors off. */
+int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *off,
+                       const int64_t *off_host, int32_t n_pairs, int32_t n_hyp, float thresh,
+                       uint64_t seed, void *ws, size_t ws_bytes, void *stream,
+                       hg_ransac_tuning *out);
+
+/* Captures hg_ransac_batched (queue reset + persistent kernel) with these
+ * exact pointers and scalars into a HIP graph (allocates, synchronises).
+ * hg_graph_launch replays it on `stream`; buffer contents may change between
+ * launches, pointers may not. */
+typedef struct hg_graph hg_graph;
+int hg_ransac_batched_graph_create(const float *corr, int64_t ld, const int64_t *off,
+                                   int32_t n_pairs, int32_t n_hyp, float thresh, uint64_t seed,
+                                   const hg_ransac_tuning *tune, float *best_H,
+                                   int32_t *best_count, int32_t *best_hyp, uint8_t *inlier_mask,
+                                   int32_t *hyp_counts, void *ws, size_t ws_bytes,
+                                   void *stream, hg_graph **out);
+int hg_graph_launch(hg_graph *g, void *stream);
+void hg_graph_destroy(hg_graph *g);
+
+/* ---- differentiable 4-point-offset pipeline -------------------------------
+ * Source: the rectangle with upper-left vertex (x0, y0), width w and aspect
+ * ratio r = width / height (Sec. 5.3). offsets: B x 4 x 2 floats, corner
+ * order TL, TR, BR, BL; target corners = source corners + offsets.
+ * hg_aca_rect_fwd: H (B x 9) by Algorithm 1 (tensorised ACA for a rectangle),
+ *   double precision inside, not rescaled (each h_ij is the polynomial of
+ *   the corners that the algorithm defines).
+ * hg_aca_rect_bwd: grad_offsets (B x 8) = (dH/d offsets)^T grad_H.          */
+int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w, float r,
+                    float *H, void *stream);
+int hg_aca_rect_bwd(const float *offsets, const float *grad_H, int32_t B, float x0, float y0,
+                    float w, float r, float *grad_offsets, void *stream);
+
+/* Photometric loss of the warp by H: for every pixel p = (x, y) of an h x w
+ * output (x = column), sample img at pi(adj(H) p) (adj(H) ~ H^-1) bilinearly,
+ * x0 = floor(x), taps outside the image reading 0;
+ * loss[b] = mean_p |I_w(p) - tgt(p)|. img, tgt: B x h x w floats.
+ * hg_warp_l1_bwd recomputes everything from H (nothing per pixel is stored)
+ * and writes grad_H (B x 9) = grad_loss[b] * dloss[b]/dH_b, with d|r|/dr =
+ * sign(r) (0 at 0) and the floor treated as constant.                        */
+int hg_warp_l1_fwd(const float *H, const float *img, const float *tgt, int32_t B, int32_t h,
+                   int32_t w, float *loss, void *stream);
+int hg_warp_l1_bwd(const float *H, const float *img, const float *tgt, const float *grad_loss,
+                   int32_t B, int32_t h, int32_t w, float *grad_H, void *stream);
+
+/* Plain stored-intermediate form of the same pipeline (for comparison):
+ * warp -> warped (B x h x w) ; L1 -> loss ; its backward -> grad_warped ;
+ * warp backward from grad_warped -> grad_H.                                  */
+int hg_warp_store_fwd(const float *H, const float *img, int32_t B, int32_t h, int32_t w,
+                      float *warped, void *stream);
+int hg_l1_fwd(const float *warped, const float *tgt, int32_t B, int32_t h, int32_t w,
+              float *loss, void *stream);
+int hg_l1_bwd(const float *warped, const float *tgt, const float *grad_loss, int32_t B,
+              int32_t h, int32_t w, float *grad_warped, void *stream);
+int hg_warp_bwd_from_grad(const float *H, const float *img, const float *grad_warped, int32_t B,
+                          int32_t h, int32_t w, float *grad_H, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOMOG_H */

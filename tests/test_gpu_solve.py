@@ -1,0 +1,124 @@
+"""Batched 4-point solver on the GPU against the oracle (parity tests).
+
+Bar: on every quadruple not flagged near-degenerate, the Frobenius-normalised,
+sign-fixed H agrees with the float64 oracle within 1e-5; flag bits agree except
+for quadruples whose oracle minimum triangle height lies within a relative 1e-3
+of the 1e-2 px threshold."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import homography as hg
+from tests.gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def oracle_solve(src, dst, method):
+    s, d = src.astype(np.float64), dst.astype(np.float64)
+    H = hg.aca64(s, d) if method == "aca" else hg.sks64(s, d)
+    H32, ok = hg.pow2_f32(H)
+    flags = hg.degeneracy_flags(src, dst) | np.where(ok, 0, hg.FLAG_ZERO_H).astype(np.uint8)
+    return H32, flags
+
+
+def gpu_solve(src, dst, method, ld=None, offset=0):
+    import paper_2402_18008_amd as hgpu
+    n = src.shape[1]
+    ld = n if ld is None else ld
+    S = torch.full((8, ld + offset), float("nan"), device="cuda")
+    D = torch.full((8, ld + offset), float("nan"), device="cuda")
+    S[:, offset:offset + n] = torch.from_numpy(src)
+    D[:, offset:offset + n] = torch.from_numpy(dst)
+    S = S[:, offset:offset + n]
+    D = D[:, offset:offset + n]
+    H, f = hgpu.hg_solve4(S, D, method)
+    torch.cuda.synchronize()
+    return H.cpu().numpy().T.reshape(n, 3, 3), f.cpu().numpy()
+
+
+def check(src, dst, method, Hg, fg, label=""):
+    H32, fo = oracle_solve(src, dst, method)
+    mh = hg.min_height(src, dst)
+    near_thr = np.abs(mh - hg.DELTA_PX) <= 1e-3 * hg.DELTA_PX
+    bad_flags = (fg != fo) & ~near_thr
+    assert not bad_flags.any(), (label, np.nonzero(bad_flags)[0][:10], fg[bad_flags][:10], fo[bad_flags][:10])
+    ok = (fo == 0) & (fg == 0)
+    e = hg.herr(Hg[ok], H32[ok].astype(np.float64))
+    assert e.max() <= TOL, (label, e.max())
+    # and against the plain definition (normalised DLT) on the same inputs
+    e2 = hg.herr(Hg[ok], hg.dlt64(src[:, ok], dst[:, ok]))
+    assert e2.max() <= TOL, (label, e2.max())
+    return dict(max_err=float(e.max()), exact=float((Hg[ok] == H32[ok]).all(axis=(1, 2)).mean()))
+
+
+@pytest.mark.parametrize("method", ["aca", "sks"])
+def test_config0(method):
+    require_gpu()
+    src, dst, _ = synth.config0()
+    announce(f"solve4 {method} config0 n=4096")
+    Hg, fg = gpu_solve(src, dst, method)
+    st = check(src, dst, method, Hg, fg, "config0")
+    print(method, st)
+    if method == "aca":
+        # same operation order in double precision: nearly always the same bits
+        assert st["exact"] > 0.99
+
+
+@pytest.mark.parametrize("method", ["aca", "sks"])
+@pytest.mark.parametrize("n,ld,offset", [(1, 1, 0), (3, 3, 0), (5, 8, 0), (4097, 4100, 0),
+                                         (1029, 1029, 1), (777, 800, 3)])
+def test_ragged_and_unaligned(method, n, ld, offset):
+    require_gpu()
+    src, dst, _ = synth.quadruples(n, 100 + n)
+    announce(f"solve4 {method} n={n} ld={ld} offset={offset}")
+    Hg, fg = gpu_solve(src, dst, method, ld=ld, offset=offset)
+    check(src, dst, method, Hg, fg, f"n={n}")
+
+
+def test_empty():
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    z = torch.empty((8, 0), device="cuda")
+    H, f = hgpu.hg_solve4(z, z)
+    assert H.shape == (9, 0) and f.shape == (0,)
+
+
+@pytest.mark.parametrize("method", ["aca", "sks"])
+def test_degenerate_and_nonfinite(method):
+    require_gpu()
+    src, dst, _ = synth.quadruples(64, 5)
+    # exactly collinear source triple, duplicated points, a NaN and an inf
+    src[:, 0] = [0, 0, 10, 10, 20, 20, 5, 40]          # M N P collinear
+    src[:, 1] = [1, 1, 1, 1, 50, 60, 70, 10]           # M == N
+    src[3, 2] = np.nan
+    dst[6, 3] = np.inf
+    announce(f"solve4 {method} degenerate cases")
+    Hg, fg = gpu_solve(src, dst, method)
+    assert fg[0] & 1 and fg[1] & 1
+    assert fg[2] == 6 and fg[3] == 6 and not Hg[2].any() and not Hg[3].any()
+    check(src[:, 4:], dst[:, 4:], method, Hg[4:], fg[4:])
+
+
+def test_config1_full_size_sampled():
+    """2^26 quadruples in the launch the benchmark times; every planted
+    near-degenerate set is flagged and a 1-in-1024 sample plus all flagged sets
+    match the oracle."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    n = 1 << 26
+    announce("solve4 aca config1 generating 2^26 quadruples")
+    src, dst, lab = synth.config1(n, workers=16)
+    S = torch.from_numpy(src).cuda()
+    D = torch.from_numpy(dst).cuda()
+    announce("solve4 aca config1 launch")
+    H, f = hgpu.hg_solve4(S, D, "aca")
+    torch.cuda.synchronize()
+    fg = f.cpu().numpy()
+    assert np.all(fg[lab == 1] & 1), "planted degeneracies must be flagged"
+    sel = np.unique(np.concatenate([np.arange(0, n, 1024), np.nonzero(fg)[0][:20000]]))
+    Hs = H[:, torch.from_numpy(sel).cuda()].cpu().numpy().T.reshape(-1, 3, 3)
+    st = check(src[:, sel], dst[:, sel], "aca", Hs, fg[sel], "config1")
+    print("config1", st, "flagged", int((fg != 0).sum()))

@@ -78,8 +78,8 @@ def decision_band(H, corr, tau):
     e = w^2 (dist^2 - tau^2) = w^2 (dist - tau)(dist + tau), the decision can
     only flip if |dist - tau| <= |error of e| / (w^2 (dist + tau)). That bound
     is returned, doubled for safety."""
-    H = np.abs(np.asarray(H, np.float64))
     Hs = np.asarray(H, np.float64)
+    H = np.abs(Hs)
     x1, y1, x2, y2 = (np.asarray(c, np.float64) for c in corr)
     ax1, ay1, ax2, ay2 = np.abs(x1), np.abs(y1), np.abs(x2), np.abs(y2)
     Su = H[:, 0, 0, None] * ax1 + H[:, 0, 1, None] * ay1 + H[:, 0, 2, None]

@@ -29,8 +29,11 @@ from . import homography as hg
 
 
 def square_corners(size, dtype=torch.float64):
-    s = float(size - 1)
-    return torch.tensor([[0.0, 0.0], [s, 0.0], [s, s], [0.0, s]], dtype=dtype)
+    """Corners TL, TR, BR, BL of a size x size patch, or of an h x w patch when
+    ``size`` is a pair (h, w)."""
+    h, w = (size, size) if isinstance(size, int) else size
+    a, b = float(w - 1), float(h - 1)
+    return torch.tensor([[0.0, 0.0], [a, 0.0], [a, b], [0.0, b]], dtype=dtype)
 
 
 def h_dlt(offsets, size):
@@ -62,54 +65,55 @@ def h_dlt(offsets, size):
 
 
 def h_rect(offsets, size):
-    """H from Algorithm 1 (square source, x0 = y0 = 0, w = S-1, r = 1) on torch
-    tensors; autograd gives its Jacobian."""
+    """H from Algorithm 1 (rectangle with corners at the pixel centres: x0 =
+    y0 = 0, width w-1, aspect (w-1)/(h-1)) on torch tensors; autograd gives
+    its Jacobian."""
     src = square_corners(size, offsets.dtype)
     dst = src[None] + offsets
     # Algorithm 1 takes M N P Q = TL TR BL BR
     M, N, Q, P = dst[:, 0], dst[:, 1], dst[:, 2], dst[:, 3]
     q = [M[:, 0], M[:, 1], N[:, 0], N[:, 1], P[:, 0], P[:, 1], Q[:, 0], Q[:, 1]]
-    H = hg.aca_rect_s(0.0, 0.0, float(size - 1), 1.0, q, square=True)
+    wr, hr = float(src[1, 0]), float(src[2, 1])
+    H = hg.aca_rect_s(0.0, 0.0, wr, wr / hr, q, square=(wr == hr))
     return torch.stack([torch.stack(r, dim=-1) for r in H], dim=-2)
 
 
 def bilinear_zero(img, sx, sy):
-    """Sample img (B, S, S) at (sx, sy) (B, P) with zero padding."""
-    B, S, _ = img.shape
+    """Sample img (B, h, w) at (sx, sy) (B, P) with zero padding."""
+    B, h, w = img.shape
     x0 = torch.floor(sx)
     y0 = torch.floor(sy)
     ax = sx - x0
     ay = sy - y0
-    flat = img.reshape(B, S * S)
+    flat = img.reshape(B, h * w)
     out = 0.0
     for dy, wy in ((0, 1 - ay), (1, ay)):
         for dx, wx in ((0, 1 - ax), (1, ax)):
             xi = (x0 + dx).long()
             yi = (y0 + dy).long()
-            inside = (xi >= 0) & (xi < S) & (yi >= 0) & (yi < S)
-            lin = torch.where(inside, yi * S + xi, torch.zeros_like(xi))
+            inside = (xi >= 0) & (xi < w) & (yi >= 0) & (yi < h)
+            lin = torch.where(inside, yi * w + xi, torch.zeros_like(xi))
             val = torch.gather(flat, 1, lin) * inside.to(img.dtype)
             out = out + wx * wy * val
     return out
 
 
 def warp(img, H):
-    """Source image (B, S, S) warped into the target frame: I(pi(H^-1 p))."""
-    B, S, _ = img.shape
+    """Source image (B, h, w) warped into the target frame: I(pi(H^-1 p))."""
+    B, h, w = img.shape
     G = torch.linalg.inv(H)
-    ys, xs = torch.meshgrid(torch.arange(S, dtype=H.dtype), torch.arange(S, dtype=H.dtype),
+    ys, xs = torch.meshgrid(torch.arange(h, dtype=H.dtype), torch.arange(w, dtype=H.dtype),
                             indexing="ij")
-    p = torch.stack([xs.reshape(-1), ys.reshape(-1), torch.ones(S * S, dtype=H.dtype)])
+    p = torch.stack([xs.reshape(-1), ys.reshape(-1), torch.ones(h * w, dtype=H.dtype)])
     q = G @ p                                       # (B, 3, P)
     sx = q[:, 0] / q[:, 2]
     sy = q[:, 1] / q[:, 2]
-    return bilinear_zero(img, sx, sy).reshape(B, S, S)
+    return bilinear_zero(img, sx, sy).reshape(B, h, w)
 
 
 def loss(offsets, img, tgt, solver=h_dlt):
     """Per-patch loss (B,) = mean |warp(img, H(offsets)) - tgt|."""
-    S = img.shape[-1]
-    H = solver(offsets, S)
+    H = solver(offsets, tuple(img.shape[-2:]))
     return (warp(img, H) - tgt).abs().mean(dim=(1, 2))
 
 

@@ -95,12 +95,18 @@ def _fp32_division_free(H, corr, tau, fused):
 
 
 @pytest.mark.parametrize("fused", [False, True])
-def test_decision_band_covers_float32_evaluation(fused):
-    cs = synth.config2()
-    idx, H32, flags, valid = ransac.hypotheses(cs.corr, 4096, seed=2)
+@pytest.mark.parametrize("case", ["config2", "horizon"])
+def test_decision_band_covers_float32_evaluation(fused, case):
+    # "horizon": a set whose hypotheses include one (index 3583, seed 77) that
+    # maps a sample point to w ~ 5e-9, where float32 scoring is far off
+    if case == "config2":
+        cs, nh, seed = synth.config2(), 4096, 2
+    else:
+        cs, nh, seed = synth.correspondences(1500, 0.5, 2500), 4097, 77
+    idx, H32, flags, valid = ransac.hypotheses(cs.corr, nh, seed=seed)
     tau = 3.0
     n_mis = n_band = 0
-    for a in range(0, 4096, 512):
+    for a in range(0, nh, 512):
         H = H32[a:a + 512][valid[a:a + 512]]
         d = ransac.transfer_error(H, cs.corr)
         band = ransac.decision_band(H, cs.corr, tau)

@@ -81,12 +81,17 @@ def time_launches(fn, steps, warmup, stream):
     return start.elapsed_time(stop), [a.elapsed_time(b) for a, b in evs]
 
 
-def _oracle_chunk(args):
-    src, dst = args
-    from oracle import homography as hg
+_CB = {}
+
+
+def _oracle_chunk(rng):
+    """Worker: the float64 oracle ACA on quadruples [a, b) of the arrays the
+    parent set up before forking (no copy through the pool)."""
+    a, b = rng
     import numpy as np
+    from oracle import homography as hg
     t = time.perf_counter()
-    hg.aca64(src.astype(np.float64), dst.astype(np.float64))
+    hg.aca64(_CB["src"][:, a:b].astype(np.float64), _CB["dst"][:, a:b].astype(np.float64))
     return time.perf_counter() - t
 
 
@@ -95,16 +100,154 @@ def cpu_baseline(src, dst, n_sample, workers):
     2^20 chunks over a process pool."""
     import multiprocessing as mp
     chunk = 1 << 20
-    jobs = [(src[:, a:a + chunk], dst[:, a:a + chunk]) for a in range(0, n_sample, chunk)]
+    jobs = [(a, min(a + chunk, n_sample)) for a in range(0, n_sample, chunk)] * 2
+    _CB["src"], _CB["dst"] = src, dst
     ctx = mp.get_context("fork")
-    t = time.perf_counter()
     with ctx.Pool(workers) as pool:
+        pool.map(_oracle_chunk, jobs[:workers])          # warm the workers
+        t = time.perf_counter()
         cpu_s = sum(pool.map(_oracle_chunk, jobs))
-    wall = time.perf_counter() - t
-    return dict(value=n_sample / wall, unit="homographies/s", cores=workers, kind="oracle",
-                sample=f"float64 NumPy ACA on the first {n_sample} quadruples of the same "
-                       f"workload, {len(jobs)} chunks of 2^20 over {workers} processes "
+        wall = time.perf_counter() - t
+    return dict(value=2 * n_sample / wall, unit="homographies/s", cores=workers, kind="oracle",
+                sample=f"float64 NumPy ACA, two passes over the first {n_sample} quadruples of "
+                       f"the same workload, {len(jobs)} chunks of 2^20 over {workers} processes "
                        f"({cpu_s:.1f} s of CPU time, {wall:.2f} s wall)")
+
+
+FP32_FLOP_PER_HYP_PT = 21   # 3 rows x 2 FMA, 2 FMA residuals, mul + FMA norm, 2 mul (tau w)^2
+FP32_PEAK_TFLOPS = 157.3
+
+
+def bench_ransac_single(stream):
+    """N = 2000 correspondences, 30 % inliers, 4096 hypotheses, tau = 3 px:
+    fused (reset + one kernel) against plain (solve, score, argmax, mask)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2402_18008_amd as hgpu
+    from paper_2402_18008_amd import _abi
+    cs = synth.config2()
+    corr = torch.from_numpy(cs.corr).cuda()
+    n, nh = corr.shape[1], 4096
+    ws = torch.empty(hgpu.hg_ransac_ws_bytes(n, nh), dtype=torch.uint8, device="cuda")
+    bh = torch.empty(9, device="cuda")
+    bc = torch.empty(1, dtype=torch.int32, device="cuda")
+    bi = torch.empty(1, dtype=torch.int32, device="cuda")
+    mk = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hc = torch.empty(nh, dtype=torch.int32, device="cuda")
+    res = {}
+    for name in ("hg_ransac", "hg_ransac_plain"):
+        fn = getattr(_abi.lib(), name)
+        args = (corr.data_ptr(), n, n, nh, 3.0, 2, bh.data_ptr(), bc.data_ptr(), bi.data_ptr(),
+                mk.data_ptr(), hc.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
+        t, p = time_launches(lambda: fn(*args), 200, 20, stream)
+        us = float(np.median(p) * 1e3)
+        res[name] = {"us_per_call": us, "hyp_pts_per_s": n * nh / (us * 1e-6)}
+    return {"ransac_2000x4096": {"fused": res["hg_ransac"], "plain": res["hg_ransac_plain"],
+                                 "fused_speedup": res["hg_ransac_plain"]["us_per_call"]
+                                 / res["hg_ransac"]["us_per_call"]}}
+
+
+def bench_ransac_batched(stream):
+    """512 uneven pairs (N ~ U{100..8000}), 1024 hypotheses each: the
+    persistent kernel (autotuned, replayed from a HIP graph) against a host
+    loop of 512 single-pair fused calls."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2402_18008_amd as hgpu
+    from paper_2402_18008_amd import _abi
+    cb = synth.config3()
+    corr = torch.from_numpy(cb.corr).cuda()
+    off = torch.from_numpy(cb.off).cuda()
+    nh = 1024
+    hyp_pts = float(np.diff(cb.off).sum()) * nh
+    br = hgpu.BatchedRansac(corr, off, nh, 3.0, 3)
+    tune = br.autotune(cb.off)
+    g = br.graph(tune)
+    t, p = time_launches(g.launch, 20, 3, stream)
+    ms_graph = float(np.median(p))
+    t, p = time_launches(lambda: br.run(tune), 20, 3, stream)
+    ms_direct = float(np.median(p))
+    g.close()
+    # plain per-problem form: one fused single-pair call per pair, host loop
+    total = corr.shape[1]
+    L = _abi.lib()
+    ws = torch.empty(hgpu.hg_ransac_ws_bytes(8000, nh), dtype=torch.uint8, device="cuda")
+    bh = torch.empty(9, device="cuda")
+    bc = torch.empty(1, dtype=torch.int32, device="cuda")
+    bi = torch.empty(1, dtype=torch.int32, device="cuda")
+    mk = torch.empty(total, dtype=torch.uint8, device="cuda")
+    base = corr.data_ptr()
+    calls = [(base + 4 * int(cb.off[q]), int(cb.off[q + 1] - cb.off[q]), total, nh, 3.0, 3,
+              bh.data_ptr(), bc.data_ptr(), bi.data_ptr(), mk.data_ptr() + int(cb.off[q]), None,
+              ws.data_ptr(), ws.numel(), stream.cuda_stream) for q in range(len(cb.off) - 1)]
+
+    def loop():
+        bad = 0
+        for a in calls:
+            bad |= L.hg_ransac(*a)
+        if bad:
+            raise RuntimeError("hg_ransac failed in the per-pair loop")
+    t, p = time_launches(loop, 5, 1, stream)
+    ms_plain = float(np.median(p))
+    rate = hyp_pts / (ms_graph * 1e-3)
+    return {"ransac_batched_512x1024": {
+        "hyp_pts": hyp_pts, "tuning": list(tune),
+        "persistent_graph_ms": ms_graph, "persistent_direct_ms": ms_direct,
+        "plain_host_loop_ms": ms_plain, "hyp_pts_per_s": rate,
+        "speedup_vs_plain": ms_plain / ms_graph,
+        "fp32_tflops": FP32_FLOP_PER_HYP_PT * rate / 1e12,
+        "fp32_frac_of_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_PEAK_TFLOPS}}
+
+
+def bench_diff(stream):
+    """B = 1024 patches of 128 x 128: offsets -> H -> warp -> L1, forward and
+    backward to the offsets; recompute form against the stored-intermediate
+    form."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2402_18008_amd as hgpu
+    pb = synth.config4()
+    off = torch.from_numpy(pb.offsets).cuda()
+    img = torch.from_numpy(pb.img).cuda()
+    tgt = torch.from_numpy(pb.tgt).cuda()
+    B, S = img.shape[0], img.shape[-1]
+    # inputs rotated through 4 copies so that the 256 MB last-level cache does not hold them
+    imgs = [img.clone() for _ in range(4)]
+    tgts = [tgt.clone() for _ in range(4)]
+    gl = torch.ones(B, device="cuda")
+    state = {"k": 0}
+    w = float(S - 1)
+
+    def recompute():
+        k = state["k"] = (state["k"] + 1) % 4
+        H = hgpu.hg_aca_rect_fwd(off, 0.0, 0.0, w, 1.0)
+        hgpu.hg_warp_l1_fwd(H, imgs[k], tgts[k])
+        gH = hgpu.hg_warp_l1_bwd(H, imgs[k], tgts[k], gl)
+        hgpu.hg_aca_rect_bwd(off, gH, 0.0, 0.0, w, 1.0)
+
+    def stored():
+        k = state["k"] = (state["k"] + 1) % 4
+        H = hgpu.hg_aca_rect_fwd(off, 0.0, 0.0, w, 1.0)
+        Wp = hgpu.hg_warp_store_fwd(H, imgs[k])
+        hgpu.hg_l1_fwd(Wp, tgts[k])
+        gW = hgpu.hg_l1_bwd(Wp, tgts[k], gl)
+        gH = hgpu.hg_warp_bwd_from_grad(H, imgs[k], gW)
+        hgpu.hg_aca_rect_bwd(off, gH, 0.0, 0.0, w, 1.0)
+
+    t, p = time_launches(recompute, 40, 4, stream)
+    ms_r = float(np.median(p))
+    t, p = time_launches(stored, 40, 4, stream)
+    ms_s = float(np.median(p))
+    min_bytes = 2 * B * S * S * 4          # img and tgt read once
+    return {"warp_l1_1024x128x128": {
+        "recompute_ms": ms_r, "stored_ms": ms_s, "patches_per_s": B / (ms_r * 1e-3),
+        "effective_GBps": min_bytes / (ms_r * 1e-3) / 1e9, "speedup_vs_stored": ms_s / ms_r}}
 
 
 def main():
@@ -170,7 +313,7 @@ def main():
                                f"+ flag byte out", "n": n, "method": "ACA"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "solve4_vec4_kernel<ACA>", "kernel_ms": kern_ms,
+                     "kernel": "solve4_kernel<ACA>", "kernel_ms": kern_ms,
                      "bytes_per_unit": BYTES_PER_QUAD},
     }
     extra = {}
@@ -193,10 +336,13 @@ def main():
             t, p = time_launches(lambda: hgpu.hg_solve4(s4, d4, meth, H=h4, flags=f4), 200, 20,
                                  stream)
             extra[f"{name}_4096_us_per_launch"] = float(np.median(p) * 1e3)
+        extra.update(bench_ransac_single(stream))
+        extra.update(bench_ransac_batched(stream))
+        extra.update(bench_diff(stream))
     out["extra"] = extra
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(src, dst, min(n, 1 << 25), workers)
+        out["cpu_baseline"] = cpu_baseline(src, dst, n, workers)
     print(json.dumps(out), flush=True)
 
 

@@ -65,9 +65,8 @@ int hg_version(void);
  *             8 triangles of either side has minimum height <= 1e-2 px);
  *             bit1 = non-finite input; bit2 = H was zero or non-finite and
  *             has been written as zeros.
- * Fast path when src, dst, H are 16-byte aligned, flags 4-byte aligned and
- * ld % 4 == 0; any other layout is accepted and takes a scalar path.
- * n == 0 is a no-op. Errors: NULL pointer (other than flags), n < 0, ld < n,
+ * Any alignment and any ld >= n are accepted (one quadruple per lane, 4-byte
+ * accesses). n == 0 is a no-op. Errors: NULL pointer (other than flags), n < 0, ld < n,
  * unknown method -> HG_EINVAL.                                               */
 enum { HG_ACA = 0, HG_SKS = 1 };
 enum { HG_FLAG_NEAR_DEGENERATE = 1, HG_FLAG_NONFINITE_INPUT = 2, HG_FLAG_ZERO_H = 4 };
@@ -108,15 +107,16 @@ int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
  * stride ld >= off[n_pairs]); every pair runs n_hyp hypotheses with Philox
  * counter (j, p, 0, 0). One persistent kernel drains a queue of (pair,
  * hypothesis block) items, largest pairs first; the last block to finish a
- * pair writes its mask. Results equal hg_ransac on each pair with counter
- * word 1 = p.
+ * pair writes its mask. Per pair, the arithmetic is that of hg_ransac (same
+ * device functions) with Philox counter word 1 = p; results do not depend
+ * on the tuning.
  *   off         n_pairs + 1 int64 (device); every pair needs >= 4 points.
  *   best_H      n_pairs x 9 floats; best_count, best_hyp n_pairs int32;
  *   inlier_mask off[n_pairs] bytes; hyp_counts n_pairs x n_hyp or NULL.
  *   tune        launch shape, NULL = the cached autotuned or default choice.
  *   ws          >= hg_ransac_batched_ws_bytes(n_pairs, n_hyp) bytes.       */
 typedef struct {
-  int32_t pts_per_lane;    /* points held in registers per lane: 4 or 8     */
+  int32_t pts_per_lane;    /* points held in registers per lane: 8 or 16    */
   int32_t hyps_per_block;  /* hypotheses per work item: 16, 32 or 64         */
   int32_t blocks_per_cu;   /* persistent blocks per compute unit: 1..8       */
   int32_t reserved;        /* 0                                              */
@@ -156,38 +156,45 @@ void hg_graph_destroy(hg_graph *g);
  * Source: the rectangle with upper-left vertex (x0, y0), width w and aspect
  * ratio r = width / height (Sec. 5.3). offsets: B x 4 x 2 floats, corner
  * order TL, TR, BR, BL; target corners = source corners + offsets.
- * hg_aca_rect_fwd: H (B x 9) by Algorithm 1 (tensorised ACA for a rectangle),
- *   double precision inside, not rescaled (each h_ij is the polynomial of
- *   the corners that the algorithm defines).
- * hg_aca_rect_bwd: grad_offsets (B x 8) = (dH/d offsets)^T grad_H.          */
+ * hg_aca_rect_fwd: H (B x 9 doubles) by Algorithm 1 (tensorised ACA for a
+ *   rectangle), double precision inside, not rescaled (each h_ij is the
+ *   polynomial of the corners that the algorithm defines).
+ * hg_aca_rect_bwd: grad_offsets (B x 8 floats) = (dH/d offsets)^T grad_H,
+ *   grad_H B x 9 doubles.
+ * Errors: B < 0, w or r not finite and > 0, non-finite x0/y0, NULL pointer
+ * with B > 0 -> HG_EINVAL; B == 0 is a no-op.                                */
 int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w, float r,
-                    float *H, void *stream);
-int hg_aca_rect_bwd(const float *offsets, const float *grad_H, int32_t B, float x0, float y0,
+                    double *H, void *stream);
+int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32_t B, float x0, float y0,
                     float w, float r, float *grad_offsets, void *stream);
 
-/* Photometric loss of the warp by H: for every pixel p = (x, y) of an h x w
- * output (x = column), sample img at pi(adj(H) p) (adj(H) ~ H^-1) bilinearly,
- * x0 = floor(x), taps outside the image reading 0;
- * loss[b] = mean_p |I_w(p) - tgt(p)|. img, tgt: B x h x w floats.
+/* Photometric loss of the warp by H (B x 9 doubles): for every pixel
+ * p = (x, y) of an h x w output (x = column), sample img at pi(adj(H) p)
+ * (adj(H) ~ H^-1) bilinearly, x0 = floor(x), taps outside the image reading
+ * 0; loss[b] = mean_p |I_w(p) - tgt(p)| (float). img, tgt: B x h x w floats.
+ * Per-pixel arithmetic is double precision.
  * hg_warp_l1_bwd recomputes everything from H (nothing per pixel is stored)
- * and writes grad_H (B x 9) = grad_loss[b] * dloss[b]/dH_b, with d|r|/dr =
- * sign(r) (0 at 0) and the floor treated as constant.                        */
-int hg_warp_l1_fwd(const float *H, const float *img, const float *tgt, int32_t B, int32_t h,
+ * and writes grad_H (B x 9 doubles) = grad_loss[b] * dloss[b]/dH_b, with
+ * d|r|/dr = sign(r) (0 at 0) and the floor treated as constant.
+ * Errors: B < 0, h or w outside [1, 32768], NULL pointer with B > 0 ->
+ * HG_EINVAL; B == 0 is a no-op.                                             */
+int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t B, int32_t h,
                    int32_t w, float *loss, void *stream);
-int hg_warp_l1_bwd(const float *H, const float *img, const float *tgt, const float *grad_loss,
-                   int32_t B, int32_t h, int32_t w, float *grad_H, void *stream);
+int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const float *grad_loss,
+                   int32_t B, int32_t h, int32_t w, double *grad_H, void *stream);
 
 /* Plain stored-intermediate form of the same pipeline (for comparison):
- * warp -> warped (B x h x w) ; L1 -> loss ; its backward -> grad_warped ;
- * warp backward from grad_warped -> grad_H.                                  */
-int hg_warp_store_fwd(const float *H, const float *img, int32_t B, int32_t h, int32_t w,
+ * warp -> warped (B x h x w floats) ; L1 -> loss ; its backward ->
+ * grad_warped (floats) ; warp backward from grad_warped -> grad_H (doubles).
+ * Same conventions as above; the stored warp is rounded to float.           */
+int hg_warp_store_fwd(const double *H, const float *img, int32_t B, int32_t h, int32_t w,
                       float *warped, void *stream);
 int hg_l1_fwd(const float *warped, const float *tgt, int32_t B, int32_t h, int32_t w,
               float *loss, void *stream);
 int hg_l1_bwd(const float *warped, const float *tgt, const float *grad_loss, int32_t B,
               int32_t h, int32_t w, float *grad_warped, void *stream);
-int hg_warp_bwd_from_grad(const float *H, const float *img, const float *grad_warped, int32_t B,
-                          int32_t h, int32_t w, float *grad_H, void *stream);
+int hg_warp_bwd_from_grad(const double *H, const float *img, const float *grad_warped, int32_t B,
+                          int32_t h, int32_t w, double *grad_H, void *stream);
 
 #ifdef __cplusplus
 }

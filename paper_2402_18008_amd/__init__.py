@@ -7,6 +7,8 @@ in the library's HIP kernels. Function names match the C entry points.
 """
 from __future__ import annotations
 
+import ctypes as C
+
 import torch
 
 from . import _abi
@@ -60,3 +62,279 @@ def hg_solve4(src, dst, method=HG_ACA, H=None, flags=None, stream=None):
 
 
 solve4 = hg_solve4
+
+
+# ---- RANSAC ----------------------------------------------------------------
+
+def _corr_planes(corr):
+    ld = _planes(corr, "corr", 4)
+    return ld, corr.shape[1]
+
+
+def hg_ransac_ws_bytes(n_pts, n_hyp):
+    return int(_abi.lib().hg_ransac_ws_bytes(int(n_pts), int(n_hyp)))
+
+
+def _ws(nbytes, device, ws):
+    if ws is None:
+        # 256-byte aligned: torch's caching allocator returns aligned blocks
+        ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    _dev(ws, "ws", torch.uint8)
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace of {nbytes} bytes needed, {ws.numel()} given")
+    return ws
+
+
+def _ransac(name, corr, n_hyp, thresh, seed, want_counts, ws, stream):
+    ld, n = _corr_planes(corr)
+    dev = corr.device
+    ws = _ws(hg_ransac_ws_bytes(n, n_hyp), dev, ws)
+    out = dict(best_H=torch.empty(9, dtype=torch.float32, device=dev),
+               best_count=torch.empty(1, dtype=torch.int32, device=dev),
+               best_hyp=torch.empty(1, dtype=torch.int32, device=dev),
+               mask=torch.empty(n, dtype=torch.uint8, device=dev),
+               hyp_counts=(torch.empty(n_hyp, dtype=torch.int32, device=dev)
+                           if want_counts else None))
+    hc = out["hyp_counts"]
+    _abi.call(name, corr.data_ptr(), n, ld, int(n_hyp), float(thresh), int(seed) & (2**64 - 1),
+              out["best_H"].data_ptr(), out["best_count"].data_ptr(), out["best_hyp"].data_ptr(),
+              out["mask"].data_ptr(), hc.data_ptr() if hc is not None else None, ws.data_ptr(),
+              ws.numel(), _stream(stream))
+    return out
+
+
+def hg_ransac(corr, n_hyp, thresh, seed, hyp_counts=True, ws=None, stream=None):
+    """Fused single-pair RANSAC. ``corr``: (4, n) float32 planes x1 y1 x2 y2.
+    Returns a dict of device tensors: best_H (9,), best_count (1,), best_hyp
+    (1,), mask (n,) uint8 and hyp_counts (n_hyp,) or None."""
+    return _ransac("hg_ransac", corr, n_hyp, thresh, seed, hyp_counts, ws, stream)
+
+
+def hg_ransac_plain(corr, n_hyp, thresh, seed, hyp_counts=True, ws=None, stream=None):
+    """Unfused single-pair RANSAC (solve, score, argmax, mask kernels); same
+    results as ``hg_ransac``."""
+    return _ransac("hg_ransac_plain", corr, n_hyp, thresh, seed, hyp_counts, ws, stream)
+
+
+def hg_ransac_batched_ws_bytes(n_pairs, n_hyp):
+    return int(_abi.lib().hg_ransac_batched_ws_bytes(int(n_pairs), int(n_hyp)))
+
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, Tuning):
+        return tune
+    return Tuning(*(int(v) for v in tune), *([0] * (4 - len(tune))))
+
+
+class BatchedRansac:
+    """Device buffers and launcher for RANSAC over many uneven pairs.
+
+    ``corr`` (4, total) float32 planes; ``off`` (n_pairs + 1,) int64 on the
+    device. Outputs (allocated here): best_H (n_pairs, 9), best_count,
+    best_hyp (n_pairs,), mask (total,) and hyp_counts (n_pairs, n_hyp) or None.
+    """
+
+    def __init__(self, corr, off, n_hyp, thresh, seed, hyp_counts=False):
+        self.ld, self.total = _corr_planes(corr)
+        _dev(off, "off", torch.int64)
+        self.corr, self.off = corr, off
+        self.n_pairs = off.numel() - 1
+        self.n_hyp, self.thresh, self.seed = int(n_hyp), float(thresh), int(seed) & (2**64 - 1)
+        dev = corr.device
+        self.ws = _ws(hg_ransac_batched_ws_bytes(self.n_pairs, self.n_hyp), dev, None)
+        self.best_H = torch.empty((self.n_pairs, 9), dtype=torch.float32, device=dev)
+        self.best_count = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        self.best_hyp = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        self.mask = torch.empty(self.total, dtype=torch.uint8, device=dev)
+        self.hyp_counts = (torch.empty((self.n_pairs, self.n_hyp), dtype=torch.int32, device=dev)
+                           if hyp_counts else None)
+
+    def _args(self):
+        hc = self.hyp_counts
+        return (self.best_H.data_ptr(), self.best_count.data_ptr(), self.best_hyp.data_ptr(),
+                self.mask.data_ptr(), hc.data_ptr() if hc is not None else None,
+                self.ws.data_ptr(), self.ws.numel())
+
+    def run(self, tune=None, stream=None):
+        """hg_ransac_batched (persistent kernel) on the current stream."""
+        t = _tuning(tune)
+        _abi.call("hg_ransac_batched", self.corr.data_ptr(), self.ld, self.off.data_ptr(),
+                  self.n_pairs, self.n_hyp, self.thresh, self.seed,
+                  None if t is None else C.byref(t), *self._args(), _stream(stream))
+        return self
+
+    def autotune(self, off_host, stream=None):
+        """hg_ransac_autotune on this problem; returns (pts_per_lane,
+        hyps_per_block, blocks_per_cu)."""
+        oh = torch.as_tensor(off_host, dtype=torch.int64).contiguous()
+        t = Tuning()
+        _abi.call("hg_ransac_autotune", self.corr.data_ptr(), self.ld, self.off.data_ptr(),
+                  C.c_void_p(oh.data_ptr()), self.n_pairs, self.n_hyp, self.thresh, self.seed,
+                  self.ws.data_ptr(), self.ws.numel(), _stream(stream), C.byref(t))
+        return (t.pts_per_lane, t.hyps_per_block, t.blocks_per_cu)
+
+    def graph(self, tune=None, stream=None):
+        """Capture into a HIP graph (hg_ransac_batched_graph_create)."""
+        return RansacGraph(self, tune, stream)
+
+
+class RansacGraph:
+    def __init__(self, br, tune=None, stream=None):
+        t = _tuning(tune)
+        h = C.c_void_p()
+        _abi.call("hg_ransac_batched_graph_create", br.corr.data_ptr(), br.ld, br.off.data_ptr(),
+                  br.n_pairs, br.n_hyp, br.thresh, br.seed, None if t is None else C.byref(t),
+                  *br._args(), _stream(stream), C.byref(h))
+        self.h = h
+        self.owner = br          # keeps the captured buffers alive
+
+    def launch(self, stream=None):
+        _abi.call("hg_graph_launch", self.h, _stream(stream))
+
+    def close(self):
+        if self.h:
+            _abi.lib().hg_graph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- differentiable 4-point-offset pipeline ----------------------------------
+
+def _c(t, name, dtype=torch.float32):
+    _dev(t, name, dtype)
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def hg_aca_rect_fwd(offsets, x0, y0, w, r, stream=None):
+    """H (B, 9) float64 from offsets (B, 4, 2) float32 [TL, TR, BR, BL] by
+    Algorithm 1."""
+    _c(offsets, "offsets")
+    B = offsets.shape[0]
+    H = torch.empty((B, 9), dtype=torch.float64, device=offsets.device)
+    _abi.call("hg_aca_rect_fwd", offsets.data_ptr(), B, float(x0), float(y0), float(w), float(r),
+              H.data_ptr(), _stream(stream))
+    return H
+
+
+def hg_aca_rect_bwd(offsets, grad_H, x0, y0, w, r, stream=None):
+    _c(offsets, "offsets")
+    _c(grad_H, "grad_H", torch.float64)
+    B = offsets.shape[0]
+    g = torch.empty((B, 4, 2), dtype=torch.float32, device=offsets.device)
+    _abi.call("hg_aca_rect_bwd", offsets.data_ptr(), grad_H.data_ptr(), B, float(x0), float(y0),
+              float(w), float(r), g.data_ptr(), _stream(stream))
+    return g
+
+
+def _img3(img, name):
+    _c(img, name)
+    if img.dim() != 3:
+        raise ValueError(f"{name} must be (B, h, w)")
+    return img.shape
+
+
+def hg_warp_l1_fwd(H, img, tgt, stream=None):
+    B, h, w = _img3(img, "img")
+    _img3(tgt, "tgt")
+    _c(H, "H", torch.float64)
+    loss = torch.empty(B, dtype=torch.float32, device=img.device)
+    _abi.call("hg_warp_l1_fwd", H.data_ptr(), img.data_ptr(), tgt.data_ptr(), B, h, w,
+              loss.data_ptr(), _stream(stream))
+    return loss
+
+
+def hg_warp_l1_bwd(H, img, tgt, grad_loss, stream=None):
+    B, h, w = _img3(img, "img")
+    _img3(tgt, "tgt")
+    _c(H, "H", torch.float64)
+    _c(grad_loss, "grad_loss")
+    gH = torch.empty((B, 9), dtype=torch.float64, device=img.device)
+    _abi.call("hg_warp_l1_bwd", H.data_ptr(), img.data_ptr(), tgt.data_ptr(),
+              grad_loss.data_ptr(), B, h, w, gH.data_ptr(), _stream(stream))
+    return gH
+
+
+def hg_warp_store_fwd(H, img, stream=None):
+    B, h, w = _img3(img, "img")
+    out = torch.empty_like(img)
+    _abi.call("hg_warp_store_fwd", _c(H, "H", torch.float64).data_ptr(), img.data_ptr(), B, h, w,
+              out.data_ptr(), _stream(stream))
+    return out
+
+
+def hg_l1_fwd(warped, tgt, stream=None):
+    B, h, w = _img3(warped, "warped")
+    _img3(tgt, "tgt")
+    loss = torch.empty(B, dtype=torch.float32, device=warped.device)
+    _abi.call("hg_l1_fwd", warped.data_ptr(), tgt.data_ptr(), B, h, w, loss.data_ptr(),
+              _stream(stream))
+    return loss
+
+
+def hg_l1_bwd(warped, tgt, grad_loss, stream=None):
+    B, h, w = _img3(warped, "warped")
+    g = torch.empty_like(warped)
+    _abi.call("hg_l1_bwd", warped.data_ptr(), _c(tgt, "tgt").data_ptr(),
+              _c(grad_loss, "grad_loss").data_ptr(), B, h, w, g.data_ptr(), _stream(stream))
+    return g
+
+
+def hg_warp_bwd_from_grad(H, img, grad_warped, stream=None):
+    B, h, w = _img3(img, "img")
+    gH = torch.empty((B, 9), dtype=torch.float64, device=img.device)
+    _abi.call("hg_warp_bwd_from_grad", _c(H, "H", torch.float64).data_ptr(), img.data_ptr(),
+              _c(grad_warped, "grad_warped").data_ptr(), B, h, w, gH.data_ptr(), _stream(stream))
+    return gH
+
+
+class ACARect(torch.autograd.Function):
+    """offsets (B, 4, 2) float32 -> H (B, 9) float64 by Algorithm 1; backward
+    by the hand-written reverse-mode kernel."""
+
+    @staticmethod
+    def forward(ctx, offsets, x0, y0, w, r):
+        offsets = offsets.contiguous()
+        ctx.save_for_backward(offsets)
+        ctx.rect = (x0, y0, w, r)
+        return hg_aca_rect_fwd(offsets, x0, y0, w, r)
+
+    @staticmethod
+    def backward(ctx, grad_H):
+        (offsets,) = ctx.saved_tensors
+        g = hg_aca_rect_bwd(offsets, grad_H.to(torch.float64).contiguous(), *ctx.rect)
+        return g, None, None, None, None
+
+
+class WarpL1(torch.autograd.Function):
+    """(H, img, tgt) -> per-patch L1 loss of the warp; the backward recomputes
+    every per-pixel quantity from H (nothing per pixel is saved)."""
+
+    @staticmethod
+    def forward(ctx, H, img, tgt):
+        H, img, tgt = H.contiguous(), img.contiguous(), tgt.contiguous()
+        ctx.save_for_backward(H, img, tgt)
+        return hg_warp_l1_fwd(H, img, tgt)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        H, img, tgt = ctx.saved_tensors
+        gl = grad_loss.to(torch.float32).contiguous()
+        return hg_warp_l1_bwd(H, img, tgt, gl), None, None
+
+
+def photometric_loss(offsets, img, tgt):
+    """Per-patch loss of the 4-point-offset pipeline for h x w patches with
+    corners at the pixel centres (0, 0) .. (w-1, h-1); differentiable in
+    offsets."""
+    h, w = img.shape[-2:]
+    H = ACARect.apply(offsets, 0.0, 0.0, float(w - 1), float(w - 1) / float(h - 1))
+    return WarpL1.apply(H, img, tgt)

@@ -1,0 +1,513 @@
+// Differentiable 4-point-offset pipeline: offsets -> H (Algorithm 1, the
+// tensorised ACA for a rectangle) -> bilinear inverse warp -> L1 loss, with
+// hand-written backward kernels that recompute per-pixel state from H.
+//
+// H is carried in double precision between the stages, and every per-pixel
+// step (sample position, bilinear weights, residual, gradient terms) runs in
+// double on the float images: a float sample position (error ~1e-5 px) would
+// move pixels across the kinks of the bilinear and L1 terms and change the
+// gradient by ~1e-3 relative. One 256-thread workgroup per patch; per-patch
+// sums are accumulated per thread and across the workgroup in double.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace hg {
+
+constexpr int kDiffThreads = 256;
+
+// Target corners from the offsets (TL, TR, BR, BL) of the rectangle with
+// upper-left (x0, y0), width w and aspect ratio r, as ACA points M N P Q.
+struct RectCorners {
+  double M2x, M2y, N2x, N2y, P2x, P2y, Q2x, Q2y;
+};
+
+__device__ __forceinline__ RectCorners rect_targets(const float *o, double x0, double y0, double w,
+                                                    double r) {
+  const double hgt = w / r;
+  RectCorners c;
+  c.M2x = x0 + static_cast<double>(o[0]);
+  c.M2y = y0 + static_cast<double>(o[1]);
+  c.N2x = x0 + w + static_cast<double>(o[2]);
+  c.N2y = y0 + static_cast<double>(o[3]);
+  c.Q2x = x0 + w + static_cast<double>(o[4]);
+  c.Q2y = y0 + hgt + static_cast<double>(o[5]);
+  c.P2x = x0 + static_cast<double>(o[6]);
+  c.P2y = y0 + hgt + static_cast<double>(o[7]);
+  return c;
+}
+
+// Algorithm 1: H = [h1 h2 h3] (columns) from the target corners.
+__device__ __forceinline__ void rect_aca(const RectCorners &k, double x0, double y0, double w,
+                                         double r, double H[9]) {
+  const double d1[3] = {k.N2x - k.M2x, k.P2x - k.M2x, k.Q2x - k.M2x};
+  const double d2[3] = {k.N2y - k.M2y, k.P2y - k.M2y, k.Q2y - k.M2y};
+  const double c0 = d1[1] * d2[2] - d1[2] * d2[1];
+  const double c1 = d1[2] * d2[0] - d1[0] * d2[2];
+  const double c2 = d1[0] * d2[1] - d1[1] * d2[0];
+  const double S = c0 + c1 + c2;
+  const double b[3] = {S * k.M2x, S * k.M2y, S};
+  const double h1[3] = {c0 * k.N2x - b[0], c0 * k.N2y - b[1], c0 - b[2]};
+  const double h2[3] = {r * (c1 * k.P2x - b[0]), r * (c1 * k.P2y - b[1]), r * (c1 - b[2])};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    H[3 * i + 0] = h1[i];
+    H[3 * i + 1] = h2[i];
+    H[3 * i + 2] = w * b[i] - x0 * h1[i] - y0 * h2[i];
+  }
+}
+
+__global__ void rect_fwd_kernel(const float *__restrict__ off, int B, double x0, double y0,
+                                double w, double r, double *__restrict__ H) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const RectCorners k = rect_targets(off + 8 * b, x0, y0, w, r);
+  double h[9];
+  rect_aca(k, x0, y0, w, r, h);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) H[9 * b + i] = h[i];
+}
+
+// Reverse mode through Algorithm 1 (each step's adjoint in reverse order).
+__global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__restrict__ gH, int B,
+                                double x0, double y0, double w, double r,
+                                float *__restrict__ goff) {
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= B) return;
+  const RectCorners k = rect_targets(off + 8 * bi, x0, y0, w, r);
+  const double d1[3] = {k.N2x - k.M2x, k.P2x - k.M2x, k.Q2x - k.M2x};
+  const double d2[3] = {k.N2y - k.M2y, k.P2y - k.M2y, k.Q2y - k.M2y};
+  const double c0 = d1[1] * d2[2] - d1[2] * d2[1];
+  const double c1 = d1[2] * d2[0] - d1[0] * d2[2];
+  const double c2 = d1[0] * d2[1] - d1[1] * d2[0];
+  const double S = c0 + c1 + c2;
+  double g1[3], g2[3], g3[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g1[i] = gH[9 * bi + 3 * i + 0];
+    g2[i] = gH[9 * bi + 3 * i + 1];
+    g3[i] = gH[9 * bi + 3 * i + 2];
+  }
+  double gb[3], gM2x = 0, gM2y = 0, gN2x = 0, gN2y = 0, gP2x = 0, gP2y = 0, gQ2x = 0, gQ2y = 0;
+  // h3 = w b - x0 h1 - y0 h2
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gb[i] = w * g3[i];
+    g1[i] -= x0 * g3[i];
+    g2[i] -= y0 * g3[i];
+  }
+  // h2 = r (c1 p2 - b), p2 = (P2x, P2y, 1)
+  double e[3] = {r * g2[0], r * g2[1], r * g2[2]};
+  double gc1 = e[0] * k.P2x + e[1] * k.P2y + e[2];
+  gP2x += e[0] * c1;
+  gP2y += e[1] * c1;
+  // h1 = c0 n2 - b, n2 = (N2x, N2y, 1)
+  double gc0 = g1[0] * k.N2x + g1[1] * k.N2y + g1[2];
+  gN2x += g1[0] * c0;
+  gN2y += g1[1] * c0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gb[i] -= e[i] + g1[i];
+  // b = S m2, m2 = (M2x, M2y, 1)
+  const double gS = gb[0] * k.M2x + gb[1] * k.M2y + gb[2];
+  gM2x += gb[0] * S;
+  gM2y += gb[1] * S;
+  gc0 += gS;
+  gc1 += gS;
+  const double gc2 = gS;
+  // c = d1 x d2
+  double gd1[3] = {0, 0, 0}, gd2[3] = {0, 0, 0};
+  gd1[1] += gc0 * d2[2];
+  gd2[2] += gc0 * d1[1];
+  gd1[2] -= gc0 * d2[1];
+  gd2[1] -= gc0 * d1[2];
+  gd1[2] += gc1 * d2[0];
+  gd2[0] += gc1 * d1[2];
+  gd1[0] -= gc1 * d2[2];
+  gd2[2] -= gc1 * d1[0];
+  gd1[0] += gc2 * d2[1];
+  gd2[1] += gc2 * d1[0];
+  gd1[1] -= gc2 * d2[0];
+  gd2[0] -= gc2 * d1[1];
+  // d1 = (N2x, P2x, Q2x) - M2x, d2 likewise in y
+  gN2x += gd1[0];
+  gP2x += gd1[1];
+  gQ2x += gd1[2];
+  gM2x -= gd1[0] + gd1[1] + gd1[2];
+  gN2y += gd2[0];
+  gP2y += gd2[1];
+  gQ2y += gd2[2];
+  gM2y -= gd2[0] + gd2[1] + gd2[2];
+  float *g = goff + 8 * bi;   // TL TR BR BL = M N Q P
+  g[0] = static_cast<float>(gM2x);
+  g[1] = static_cast<float>(gM2y);
+  g[2] = static_cast<float>(gN2x);
+  g[3] = static_cast<float>(gN2y);
+  g[4] = static_cast<float>(gQ2x);
+  g[5] = static_cast<float>(gQ2y);
+  g[6] = static_cast<float>(gP2x);
+  g[7] = static_cast<float>(gP2y);
+}
+
+// adj(H) (cyclic cofactor form) scaled by 2^-e so that max|G| is in [0.5, 1);
+// returns e (0 if G is zero or not finite, then G = 0).
+__device__ __forceinline__ int adjugate_scaled(const double *Hd, double G[9]) {
+  double H[3][3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) H[i / 3][i % 3] = Hd[i];
+  double m = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int a = (j + 1) % 3, b2 = (j + 2) % 3, c = (i + 1) % 3, d = (i + 2) % 3;
+      const double g = H[a][c] * H[b2][d] - H[a][d] * H[b2][c];
+      G[3 * i + j] = g;
+      bad |= !(fabs(g) <= 1.7976931348623157e308);
+      m = fmax(m, fabs(g));
+    }
+  if (bad || m == 0.0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) G[i] = 0.0;
+    return 0;
+  }
+  int e;
+  (void)frexp(m, &e);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i] = ldexp(G[i], -e);
+  return e;
+}
+
+// Bilinear sample with zero padding and its gradient with respect to (sx, sy).
+struct Tap {
+  double v, dvdx, dvdy;
+};
+
+template <bool GRAD>
+__device__ __forceinline__ Tap bilinear(const float *__restrict__ img, int h, int w, double sx,
+                                        double sy) {
+  Tap t = {0.0, 0.0, 0.0};
+  if (!(fabs(sx) < 1.0e6) || !(fabs(sy) < 1.0e6)) return t;   // far outside or nan
+  const double fx = floor(sx), fy = floor(sy);
+  const double ax = sx - fx, ay = sy - fy;
+  const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
+  const bool x0in = ix >= 0 && ix < w, x1in = ix + 1 >= 0 && ix + 1 < w;
+  const bool y0in = iy >= 0 && iy < h, y1in = iy + 1 >= 0 && iy + 1 < h;
+  // clamped addresses keep every load inside the image; out-of-range taps read 0
+  const int cx0 = min(max(ix, 0), w - 1), cx1 = min(max(ix + 1, 0), w - 1);
+  const int cy0 = min(max(iy, 0), h - 1), cy1 = min(max(iy + 1, 0), h - 1);
+  const float L00 = img[cy0 * w + cx0], L01 = img[cy0 * w + cx1];
+  const float L10 = img[cy1 * w + cx0], L11 = img[cy1 * w + cx1];
+  const double I00 = (y0in && x0in) ? static_cast<double>(L00) : 0.0;
+  const double I01 = (y0in && x1in) ? static_cast<double>(L01) : 0.0;
+  const double I10 = (y1in && x0in) ? static_cast<double>(L10) : 0.0;
+  const double I11 = (y1in && x1in) ? static_cast<double>(L11) : 0.0;
+  const double top = fma(ax, I01 - I00, I00);
+  const double bot = fma(ax, I11 - I10, I10);
+  t.v = fma(ay, bot - top, top);
+  if (GRAD) {
+    t.dvdx = fma(ay, (I11 - I10) - (I01 - I00), I01 - I00);
+    t.dvdy = bot - top;
+  }
+  return t;
+}
+
+// Workgroup sum of NV per-thread float partials, in double. Result valid in
+// thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[NV]) {
+  __shared__ double red[kDiffThreads / 64][NV];
+  double s[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    s[k] = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_down(s[k], o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave][k] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int q = 0; q < kDiffThreads / 64; ++q) t += red[q][k];
+      out[k] = t;
+    }
+  }
+}
+
+// Per-patch G = 2^-e adj(H) shared by the workgroup.
+__device__ __forceinline__ void load_G(const double *H, double G[9], int &e) {
+  __shared__ double Gs[9];
+  __shared__ int es;
+  if (threadIdx.x == 0) {
+    double g[9];
+    es = adjugate_scaled(H, g);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Gs[i] = g[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i] = Gs[i];
+  e = es;
+}
+
+__device__ __forceinline__ void sample_pos(const double *G, double x, double y, double &sx,
+                                           double &sy, double &iq2) {
+  const double q0 = fma(G[0], x, fma(G[1], y, G[2]));
+  const double q1 = fma(G[3], x, fma(G[4], y, G[5]));
+  const double q2 = fma(G[6], x, fma(G[7], y, G[8]));
+  iq2 = 1.0 / q2;
+  sx = q0 * iq2;
+  sy = q1 * iq2;
+}
+
+// MODE 0: loss only; 2: stored warp only (rounded to float).
+template <int MODE>
+__global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__restrict__ H,
+                                                                const float *__restrict__ img,
+                                                                const float *__restrict__ tgt,
+                                                                int h, int w,
+                                                                float *__restrict__ loss,
+                                                                float *__restrict__ warped) {
+  const int b = blockIdx.x;
+  double G[9];
+  int e;
+  load_G(H + 9 * b, G, e);
+  const int64_t P = static_cast<int64_t>(h) * w;
+  const float *I = img + b * P;
+  double acc[1] = {0.0};
+  int y = static_cast<int>(threadIdx.x) / w, x = static_cast<int>(threadIdx.x) % w;
+  const int step_y = kDiffThreads / w, step_x = kDiffThreads % w;
+  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
+    double sx, sy, iq2;
+    sample_pos(G, static_cast<double>(x), static_cast<double>(y), sx, sy, iq2);
+    const double v = bilinear<false>(I, h, w, sx, sy).v;
+    if (MODE == 2) warped[b * P + i] = static_cast<float>(v);
+    if (MODE == 0) acc[0] += fabs(v - static_cast<double>(tgt[b * P + i]));
+    x += step_x;
+    y += step_y;
+    if (x >= w) {
+      x -= w;
+      ++y;
+    }
+  }
+  if (MODE == 0) {
+    double s[1];
+    block_sum<1>(acc, s);
+    if (threadIdx.x == 0) loss[b] = static_cast<float>(s[0] / static_cast<double>(P));
+  }
+}
+
+// dL/dH from dL/dG (G = 2^-e adj(H)), thread 0, double precision.
+__device__ __forceinline__ void adjugate_backward(const double *Hd, const double gG[9], int e,
+                                                  double *gHout) {
+  double H[3][3], gH[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) H[i / 3][i % 3] = Hd[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double g = ldexp(gG[3 * i + j], -e);
+      const int a = (j + 1) % 3, b2 = (j + 2) % 3, c = (i + 1) % 3, d = (i + 2) % 3;
+      gH[a][c] += g * H[b2][d];
+      gH[b2][d] += g * H[a][c];
+      gH[a][d] -= g * H[b2][c];
+      gH[b2][c] -= g * H[a][d];
+    }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gHout[i] = gH[i / 3][i % 3];
+}
+
+// FROM_STORED = false: recompute r = I_w - T and use sign(r) grad_loss / (h w);
+// FROM_STORED = true: read dL/dI_w from grad_warped.
+template <bool FROM_STORED>
+__global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
+    const double *__restrict__ H, const float *__restrict__ img, const float *__restrict__ tgt,
+    const float *__restrict__ grad_loss, const float *__restrict__ grad_warped, int h, int w,
+    double *__restrict__ grad_H) {
+  const int b = blockIdx.x;
+  double G[9];
+  int e;
+  load_G(H + 9 * b, G, e);
+  const int64_t P = static_cast<int64_t>(h) * w;
+  const float *I = img + b * P;
+  const double gl = FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(P);
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int y = static_cast<int>(threadIdx.x) / w, x = static_cast<int>(threadIdx.x) % w;
+  const int step_y = kDiffThreads / w, step_x = kDiffThreads % w;
+  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
+    const double xf = static_cast<double>(x), yf = static_cast<double>(y);
+    double sx, sy, iq2;
+    sample_pos(G, xf, yf, sx, sy, iq2);
+    const Tap t = bilinear<true>(I, h, w, sx, sy);
+    double g;
+    if (FROM_STORED) {
+      g = static_cast<double>(grad_warped[b * P + i]);
+    } else {
+      const double r = t.v - static_cast<double>(tgt[b * P + i]);
+      g = (r > 0.0) ? gl : ((r < 0.0) ? -gl : 0.0);
+    }
+    const double gx = g * t.dvdx, gy = g * t.dvdy;
+    const double a0 = gx * iq2, a1 = gy * iq2;
+    const double a2 = -(gx * sx + gy * sy) * iq2;
+    acc[0] = fma(a0, xf, acc[0]);
+    acc[1] = fma(a0, yf, acc[1]);
+    acc[2] += a0;
+    acc[3] = fma(a1, xf, acc[3]);
+    acc[4] = fma(a1, yf, acc[4]);
+    acc[5] += a1;
+    acc[6] = fma(a2, xf, acc[6]);
+    acc[7] = fma(a2, yf, acc[7]);
+    acc[8] += a2;
+    x += step_x;
+    y += step_y;
+    if (x >= w) {
+      x -= w;
+      ++y;
+    }
+  }
+  double gG[9];
+  block_sum<9>(acc, gG);
+  if (threadIdx.x == 0) adjugate_backward(H + 9 * b, gG, e, grad_H + 9 * b);
+}
+
+__global__ void l1_fwd_kernel(const float *__restrict__ warped, const float *__restrict__ tgt,
+                              int64_t P, float *__restrict__ loss) {
+  const int b = blockIdx.x;
+  double acc[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads)
+    acc[0] += fabs(static_cast<double>(warped[b * P + i]) - static_cast<double>(tgt[b * P + i]));
+  double s[1];
+  block_sum<1>(acc, s);
+  if (threadIdx.x == 0) loss[b] = static_cast<float>(s[0] / static_cast<double>(P));
+}
+
+__global__ void l1_bwd_kernel(const float *__restrict__ warped, const float *__restrict__ tgt,
+                              const float *__restrict__ grad_loss, int64_t P,
+                              float *__restrict__ gw) {
+  const int b = blockIdx.x;
+  const float gl = static_cast<float>(static_cast<double>(grad_loss[b]) / static_cast<double>(P));
+  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
+    const float r = warped[b * P + i] - tgt[b * P + i];
+    gw[b * P + i] = (r > 0.0f) ? gl : ((r < 0.0f) ? -gl : 0.0f);
+  }
+}
+
+static int check_img(const void *a, const void *b2, int B, int h, int w, const char *fn) {
+  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(h >= 1 && w >= 1 && h <= 32768 && w <= 32768, "%s: image size %d x %d out of range",
+             fn, h, w);
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(a && b2, "%s: NULL pointer", fn);
+  return HG_OK;
+}
+
+static int check_rect(float w, float r, int B, const char *fn) {
+  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(std::isfinite(w) && w > 0.0f && std::isfinite(r) && r > 0.0f,
+             "%s: rectangle width and aspect ratio must be finite and > 0", fn);
+  return HG_OK;
+}
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w,
+                               float r, double *H, void *stream) {
+  clear_error();
+  if (int st = check_rect(w, r, B, "hg_aca_rect_fwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(offsets && H, "hg_aca_rect_fwd: NULL pointer");
+  HG_REQUIRE(std::isfinite(x0) && std::isfinite(y0), "hg_aca_rect_fwd: non-finite origin");
+  hipLaunchKernelGGL(rect_fwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream),
+                     offsets, B, static_cast<double>(x0), static_cast<double>(y0),
+                     static_cast<double>(w), static_cast<double>(r), H);
+  return launched("rect_fwd_kernel");
+}
+
+extern "C" int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32_t B, float x0,
+                               float y0, float w, float r, float *grad_offsets, void *stream) {
+  clear_error();
+  if (int st = check_rect(w, r, B, "hg_aca_rect_bwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(offsets && grad_H && grad_offsets, "hg_aca_rect_bwd: NULL pointer");
+  HG_REQUIRE(std::isfinite(x0) && std::isfinite(y0), "hg_aca_rect_bwd: non-finite origin");
+  hipLaunchKernelGGL(rect_bwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream),
+                     offsets, grad_H, B, static_cast<double>(x0), static_cast<double>(y0),
+                     static_cast<double>(w), static_cast<double>(r), grad_offsets);
+  return launched("rect_bwd_kernel");
+}
+
+extern "C" int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t B,
+                              int32_t h, int32_t w, float *loss, void *stream) {
+  clear_error();
+  if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_fwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(H && loss, "hg_warp_l1_fwd: NULL pointer");
+  hipLaunchKernelGGL(warp_fwd_kernel<0>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H, img,
+                     tgt, h, w, loss, nullptr);
+  return launched("warp_fwd_kernel");
+}
+
+extern "C" int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt,
+                              const float *grad_loss, int32_t B, int32_t h, int32_t w,
+                              double *grad_H, void *stream) {
+  clear_error();
+  if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_bwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(H && grad_loss && grad_H, "hg_warp_l1_bwd: NULL pointer");
+  hipLaunchKernelGGL(warp_bwd_kernel<false>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H,
+                     img, tgt, grad_loss, nullptr, h, w, grad_H);
+  return launched("warp_bwd_kernel");
+}
+
+extern "C" int hg_warp_store_fwd(const double *H, const float *img, int32_t B, int32_t h,
+                                 int32_t w, float *warped, void *stream) {
+  clear_error();
+  if (int st = check_img(img, warped, B, h, w, "hg_warp_store_fwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(H, "hg_warp_store_fwd: NULL H");
+  hipLaunchKernelGGL(warp_fwd_kernel<2>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H, img,
+                     nullptr, h, w, nullptr, warped);
+  return launched("warp_fwd_kernel<store>");
+}
+
+extern "C" int hg_l1_fwd(const float *warped, const float *tgt, int32_t B, int32_t h, int32_t w,
+                         float *loss, void *stream) {
+  clear_error();
+  if (int st = check_img(warped, tgt, B, h, w, "hg_l1_fwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(loss, "hg_l1_fwd: NULL loss");
+  hipLaunchKernelGGL(l1_fwd_kernel, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), warped, tgt,
+                     static_cast<int64_t>(h) * w, loss);
+  return launched("l1_fwd_kernel");
+}
+
+extern "C" int hg_l1_bwd(const float *warped, const float *tgt, const float *grad_loss, int32_t B,
+                         int32_t h, int32_t w, float *grad_warped, void *stream) {
+  clear_error();
+  if (int st = check_img(warped, tgt, B, h, w, "hg_l1_bwd")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(grad_loss && grad_warped, "hg_l1_bwd: NULL pointer");
+  hipLaunchKernelGGL(l1_bwd_kernel, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), warped, tgt,
+                     grad_loss, static_cast<int64_t>(h) * w, grad_warped);
+  return launched("l1_bwd_kernel");
+}
+
+extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const float *grad_warped,
+                                     int32_t B, int32_t h, int32_t w, double *grad_H,
+                                     void *stream) {
+  clear_error();
+  if (int st = check_img(img, grad_warped, B, h, w, "hg_warp_bwd_from_grad")) return st;
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(H && grad_H, "hg_warp_bwd_from_grad: NULL pointer");
+  hipLaunchKernelGGL(warp_bwd_kernel<true>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H,
+                     img, nullptr, nullptr, grad_warped, h, w, grad_H);
+  return launched("warp_bwd_kernel<stored>");
+}

@@ -1,0 +1,742 @@
+// RANSAC hypothesise-and-verify on the GPU.
+//
+// Work item = (pair, block of HB hypotheses). A 256-thread workgroup solves
+// its HB hypotheses (one per thread) into LDS, then scores them against the
+// pair's points: each lane holds P correspondences in registers, the
+// hypothesis is broadcast to scalar registers, the inlier test runs per
+// (hypothesis, point) and counts come from a wavefront ballot + popcount.
+// The per-pair argmax is an atomicMax on a packed (count, ~index) key; the last
+// workgroup to finish a pair recomputes the winning hypothesis and writes the
+// pair's inlier mask and best outputs.
+//
+// Forms:
+//  * fused single pair: grid = hypothesis blocks, plus a small reset kernel;
+//  * plain single pair: solve all -> H buffer, score, argmax, mask kernels;
+//  * batched persistent: CUs x blocks_per_cu workgroups drain an atomic queue
+//    of items ordered by pair size (largest first).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+#include "ransac_dev.hpp"
+
+namespace hg {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+struct RansacArgs {
+  const float *corr;
+  int64_t ld;
+  const int64_t *off;      // n_pairs + 1 offsets, or nullptr for one pair of n_single points
+  int32_t n_single;
+  int32_t n_pairs;
+  int32_t n_hyp;
+  int32_t n_hb;            // hypothesis blocks per pair
+  int64_t n_items;         // n_pairs * n_hb
+  float tau;
+  uint32_t k0, k1;         // Philox key (seed low / high word)
+  float *best_H;
+  int32_t *best_count;
+  int32_t *best_hyp;
+  uint8_t *mask;
+  int32_t *hyp_counts;     // may be null
+  unsigned long long *keys;
+  uint32_t *done;
+  uint32_t *queue;
+  const int32_t *order;    // pair processing order (largest first), or nullptr
+};
+
+__device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &base, uint32_t &n) {
+  if (a.off) {
+    base = a.off[p];
+    const int64_t e = a.off[p + 1];
+    const int64_t m = e - base;
+    n = (m < 0) ? 0u : (m > 0x7FFFFFFF ? 0x7FFFFFFFu : static_cast<uint32_t>(m));
+  } else {
+    base = 0;
+    n = static_cast<uint32_t>(a.n_single);
+  }
+}
+
+__device__ __forceinline__ float bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Score hypotheses Hs[0..nh) (LDS, 9 floats each; valid[h] != 0) against the
+// points [base, base + n): per-wave partial counts into part[wave][h].
+template <int P, int HB>
+__device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
+                                           const float (*Hs)[9], const uint32_t *valid, int nh,
+                                           uint32_t (*part)[HB]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
+  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
+  const float nan = __int_as_float(0x7fc00000);
+  for (uint32_t c0 = 0; c0 < n; c0 += kWaves * 64 * P) {
+    float x1[P], y1[P], x2[P], y2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const uint32_t i = c0 + (p * kWaves + wave) * 64 + lane;
+      const bool in = i < n;
+      const uint32_t j = in ? i : n - 1u;   // every load stays inside the pair
+      const float v0 = X1[j], v1 = Y1[j], v2 = X2[j], v3 = Y2[j];
+      x1[p] = in ? v0 : nan;
+      y1[p] = in ? v1 : nan;
+      x2[p] = in ? v2 : nan;
+      y2[p] = in ? v3 : nan;
+    }
+    for (int h = 0; h < nh; ++h) {
+      if (!__builtin_amdgcn_readfirstlane(valid[h])) continue;
+      float hh[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) hh[k] = bcast(Hs[h][k]);
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        cnt += __popcll(__ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p], a.tau)));
+      if (lane == 0) part[wave][h] += cnt;
+    }
+  }
+}
+
+// Shared memory of one workgroup.
+template <int HB>
+struct Smem {
+  float H[HB][9];
+  uint32_t valid[HB];
+  uint32_t part[kWaves][HB];
+  float bestH[9];
+  int64_t item;
+  uint32_t last;
+  unsigned long long key;
+};
+
+// Writes the inlier mask and best outputs of pair p (whole workgroup).
+template <int HB>
+__device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n, Smem<HB> &sm) {
+  if (threadIdx.x == 0) {
+    const unsigned long long key = atomicMax(&a.keys[p], 0ull);   // coherent read
+    sm.key = key;
+    if (key != 0ull) {
+      const uint32_t hyp = 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
+      make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, hyp, static_cast<uint32_t>(p),
+                      sm.bestH);
+      a.best_count[p] = static_cast<int32_t>((key >> 32) - 1ull);
+      a.best_hyp[p] = static_cast<int32_t>(hyp);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sm.bestH[k] = 0.0f;
+      a.best_count[p] = 0;
+      a.best_hyp[p] = -1;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) a.best_H[9 * p + threadIdx.x] = sm.bestH[threadIdx.x];
+  const bool any = sm.key != 0ull;
+  float hh[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) hh[k] = sm.bestH[k];
+  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
+  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
+  for (uint32_t i = threadIdx.x; i < n; i += kThreads)
+    a.mask[base + i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+}
+
+// Process one work item: pair rank r, hypothesis block hb.
+template <int P, int HB>
+__device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
+  const int r = static_cast<int>(item / a.n_hb);
+  const int hb = static_cast<int>(item % a.n_hb);
+  const int p = a.order ? a.order[r] : r;
+  int64_t base;
+  uint32_t n;
+  pair_range(a, p, base, n);
+  const int h0 = hb * HB;
+  const int nh = min(HB, a.n_hyp - h0);
+  // 1. solve this block's hypotheses, one per thread
+  if (threadIdx.x < HB) {
+    const int t = threadIdx.x;
+    uint32_t f = kZeroH;
+    if (t < nh)
+      f = make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, static_cast<uint32_t>(h0 + t),
+                          static_cast<uint32_t>(p), sm.H[t]);
+    sm.valid[t] = (t < nh && f == 0u) ? 1u : 0u;
+  }
+  for (int i = threadIdx.x; i < kWaves * HB; i += kThreads) sm.part[i / HB][i % HB] = 0u;
+  __syncthreads();
+  // 2. score
+  score_hyps<P, HB>(a, base, n, sm.H, sm.valid, nh, sm.part);
+  __syncthreads();
+  // 3. reduce over waves, publish counts and the argmax key
+  if (threadIdx.x < nh) {
+    const int t = threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += sm.part[w][t];
+    const bool ok = sm.valid[t] != 0u;
+    if (a.hyp_counts)
+      a.hyp_counts[static_cast<int64_t>(p) * a.n_hyp + h0 + t] = ok ? static_cast<int32_t>(c) : 0;
+    if (ok) atomicMax(&a.keys[p], pack_key(c, static_cast<uint32_t>(h0 + t)));
+  }
+  __threadfence();
+  __syncthreads();
+  // 4. the last block of this pair writes its mask
+  if (threadIdx.x == 0) sm.last = (atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1));
+  __syncthreads();
+  if (sm.last) {
+    __threadfence();
+    finish_pair<HB>(a, p, base, n, sm);
+  }
+  __syncthreads();
+}
+
+template <int P, int HB, bool PERSISTENT>
+__global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
+  __shared__ Smem<HB> sm;
+  if (!PERSISTENT) {
+    run_item<P, HB>(a, blockIdx.x, sm);
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = static_cast<int64_t>(atomicAdd(a.queue, 1u));
+    __syncthreads();
+    const int64_t item = sm.item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    run_item<P, HB>(a, item, sm);
+  }
+}
+
+// Resets keys, done counters and the queue, and ranks pairs by size
+// (largest first, ties by index) when the pair count is small enough for the
+// quadratic ranking.
+__global__ void ransac_prep_kernel(RansacArgs a, int rank) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0 && a.queue) *a.queue = 0u;
+  if (p >= a.n_pairs) return;
+  a.keys[p] = 0ull;
+  a.done[p] = 0u;
+  if (!a.order) return;
+  int32_t *order = const_cast<int32_t *>(a.order);
+  if (!rank) {
+    order[p] = p;
+    return;
+  }
+  int64_t b;
+  uint32_t np;
+  pair_range(a, p, b, np);
+  int r = 0;
+  for (int q = 0; q < a.n_pairs; ++q) {
+    uint32_t nq;
+    pair_range(a, q, b, nq);
+    r += (nq > np) || (nq == np && q < p);
+  }
+  order[r] = p;
+}
+
+// ---- plain single-pair form -------------------------------------------------
+
+__global__ void plain_solve_kernel(RansacArgs a, float *Hbuf, uint32_t *valid) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_hyp) return;
+  float h[9];
+  const uint32_t f = make_hypothesis(a.corr, a.ld, 0, static_cast<uint32_t>(a.n_single), a.k0,
+                                     a.k1, static_cast<uint32_t>(j), 0u, h);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Hbuf[9 * j + k] = h[k];
+  valid[j] = f == 0u ? 1u : 0u;
+}
+
+template <int P, int HB>
+__global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, const float *Hbuf,
+                                                               const uint32_t *valid,
+                                                               int32_t *counts) {
+  __shared__ float Hs[HB][9];
+  __shared__ uint32_t vs[HB];
+  __shared__ uint32_t part[kWaves][HB];
+  const int h0 = blockIdx.x * HB;
+  const int nh = min(HB, a.n_hyp - h0);
+  for (int i = threadIdx.x; i < HB * 9; i += kThreads)
+    Hs[i / 9][i % 9] = (i / 9 < nh) ? Hbuf[9 * h0 + i] : 0.0f;
+  for (int i = threadIdx.x; i < HB; i += kThreads) vs[i] = (i < nh) ? valid[h0 + i] : 0u;
+  for (int i = threadIdx.x; i < kWaves * HB; i += kThreads) part[i / HB][i % HB] = 0u;
+  __syncthreads();
+  score_hyps<P, HB>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vs, nh, part);
+  __syncthreads();
+  if (threadIdx.x < nh) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += part[w][threadIdx.x];
+    counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(c) : -1;
+  }
+}
+
+// One workgroup: argmax over counts (-1 = invalid), ties to the lower index.
+__global__ __launch_bounds__(kThreads) void plain_argmax_kernel(const int32_t *counts, int n_hyp,
+                                                                unsigned long long *key,
+                                                                int32_t *hyp_counts) {
+  __shared__ unsigned long long red[kThreads];
+  unsigned long long best = 0ull;
+  for (int j = threadIdx.x; j < n_hyp; j += kThreads) {
+    const int32_t c = counts[j];
+    if (hyp_counts) hyp_counts[j] = c < 0 ? 0 : c;
+    if (c >= 0) best = max(best, pack_key(static_cast<uint32_t>(c), static_cast<uint32_t>(j)));
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *key = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, const float *Hbuf,
+                                                              const unsigned long long *key) {
+  const unsigned long long k = *key;
+  const bool any = k != 0ull;
+  const uint32_t hyp = any ? 0xFFFFFFFFu - static_cast<uint32_t>(k & 0xFFFFFFFFull) : 0u;
+  float hh[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) hh[i] = any ? Hbuf[9 * hyp + i] : 0.0f;
+  if (blockIdx.x == 0 && threadIdx.x < 9) a.best_H[threadIdx.x] = hh[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.best_count[0] = any ? static_cast<int32_t>((k >> 32) - 1ull) : 0;
+    a.best_hyp[0] = any ? static_cast<int32_t>(hyp) : -1;
+  }
+  const int n = a.n_single;
+  const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+}
+
+// ---- tuning --------------------------------------------------------------
+
+struct Tune {
+  int P, HB, bpc;
+};
+
+static bool tune_valid(const hg_ransac_tuning &t) {
+  return (t.pts_per_lane == 8 || t.pts_per_lane == 16) &&
+         (t.hyps_per_block == 16 || t.hyps_per_block == 32 || t.hyps_per_block == 64) &&
+         t.blocks_per_cu >= 1 && t.blocks_per_cu <= 8;
+}
+
+static const hg_ransac_tuning kDefaultTune = {16, 32, 2, 0};
+
+typedef void (*KernelFn)(RansacArgs);
+
+template <bool PERSISTENT>
+static KernelFn pick_kernel(int P, int HB) {
+#define HG_PICK(PP, HH) \
+  if (P == PP && HB == HH) return ransac_kernel<PP, HH, PERSISTENT>;
+  HG_PICK(8, 16) HG_PICK(8, 32) HG_PICK(8, 64) HG_PICK(16, 16) HG_PICK(16, 32) HG_PICK(16, 64)
+#undef HG_PICK
+  return nullptr;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::string, hg_ransac_tuning> g_tune_cache;
+static bool g_tune_file_read = false;
+
+static std::string tune_key(int n_pairs, int n_hyp) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950:%d:%d:%d", device_cus(), n_pairs, n_hyp);
+  return buf;
+}
+
+static void read_tune_file() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char *path = getenv("HG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char key[256];
+    hg_ransac_tuning t = {0, 0, 0, 0};
+    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d ]", key, &t.pts_per_lane,
+               &t.hyps_per_block, &t.blocks_per_cu) == 4 &&
+        tune_valid(t))
+      g_tune_cache[key] = t;
+  }
+  fclose(f);
+}
+
+static void write_tune_file() {
+  const char *path = getenv("HG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto &kv : g_tune_cache) {
+    fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.pts_per_lane,
+            kv.second.hyps_per_block, kv.second.blocks_per_cu,
+            ++i < g_tune_cache.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+static hg_ransac_tuning lookup_tune(int n_pairs, int n_hyp) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  read_tune_file();
+  auto it = g_tune_cache.find(tune_key(n_pairs, n_hyp));
+  return it == g_tune_cache.end() ? kDefaultTune : it->second;
+}
+
+// ---- workspace layout ------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct BatchedWs {
+  unsigned long long *keys;
+  uint32_t *done;
+  int32_t *order;
+  uint32_t *queue;
+};
+
+static size_t batched_ws_bytes(int n_pairs) {
+  return align256(8ull * n_pairs) + align256(4ull * n_pairs) + align256(4ull * n_pairs) + 256;
+}
+
+static BatchedWs carve_batched(void *ws, int n_pairs) {
+  char *p = static_cast<char *>(ws);
+  BatchedWs w;
+  w.keys = reinterpret_cast<unsigned long long *>(p);
+  p += align256(8ull * n_pairs);
+  w.done = reinterpret_cast<uint32_t *>(p);
+  p += align256(4ull * n_pairs);
+  w.order = reinterpret_cast<int32_t *>(p);
+  p += align256(4ull * n_pairs);
+  w.queue = reinterpret_cast<uint32_t *>(p);
+  return w;
+}
+
+static size_t plain_ws_bytes(int n_hyp) {
+  return align256(36ull * n_hyp) + align256(4ull * n_hyp) + align256(4ull * n_hyp) + 256;
+}
+
+// ---- host launchers --------------------------------------------------------
+
+static int check_single(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,
+                        float *best_H, int32_t *best_count, int32_t *best_hyp, uint8_t *mask,
+                        void *ws, size_t ws_bytes, size_t need) {
+  HG_REQUIRE(corr && best_H && best_count && best_hyp && mask,
+             "hg_ransac: NULL corr or output pointer");
+  HG_REQUIRE(n_pts >= 4, "hg_ransac: n_pts = %d < 4", n_pts);
+  HG_REQUIRE(ld >= n_pts, "hg_ransac: ld < n_pts");
+  HG_REQUIRE(n_hyp >= 1, "hg_ransac: n_hyp = %d < 1", n_hyp);
+  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f, "hg_ransac: threshold must be finite and > 0");
+  if (!ws || ws_bytes < need)
+    return fail(HG_EWORKSPACE, "hg_ransac: workspace of %zu bytes needed, %zu given", need,
+                ws ? ws_bytes : static_cast<size_t>(0));
+  HG_REQUIRE(aligned(ws, 256), "hg_ransac: workspace must be 256-byte aligned");
+  return HG_OK;
+}
+
+static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, int32_t n_single,
+                            int32_t n_pairs, int32_t n_hyp, int HB, float thresh, uint64_t seed,
+                            float *best_H, int32_t *best_count, int32_t *best_hyp, uint8_t *mask,
+                            int32_t *hyp_counts) {
+  RansacArgs a;
+  a.corr = corr;
+  a.ld = ld;
+  a.off = off;
+  a.n_single = n_single;
+  a.n_pairs = n_pairs;
+  a.n_hyp = n_hyp;
+  a.n_hb = (n_hyp + HB - 1) / HB;
+  a.n_items = static_cast<int64_t>(n_pairs) * a.n_hb;
+  a.tau = thresh;
+  a.k0 = static_cast<uint32_t>(seed & 0xFFFFFFFFull);
+  a.k1 = static_cast<uint32_t>(seed >> 32);
+  a.best_H = best_H;
+  a.best_count = best_count;
+  a.best_hyp = best_hyp;
+  a.mask = mask;
+  a.hyp_counts = hyp_counts;
+  a.keys = nullptr;
+  a.done = nullptr;
+  a.queue = nullptr;
+  a.order = nullptr;
+  return a;
+}
+
+// Enqueue the batched form (prep + persistent kernel) on stream s.
+static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void *ws,
+                          hipStream_t s) {
+  RansacArgs a = a0;
+  const BatchedWs w = carve_batched(ws, a.n_pairs);
+  a.keys = w.keys;
+  a.done = w.done;
+  a.queue = w.queue;
+  a.order = w.order;
+  const int rank = a.n_pairs <= 16384 ? 1 : 0;
+  hipLaunchKernelGGL(ransac_prep_kernel, dim3((a.n_pairs + 255) / 256), dim3(256), 0, s, a, rank);
+  if (int st = launched("ransac_prep_kernel")) return st;
+  KernelFn k = pick_kernel<true>(t.pts_per_lane, t.hyps_per_block);
+  if (!k) return fail(HG_EINVAL, "unsupported tuning");
+  const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(device_cus()) * t.blocks_per_cu,
+                                           std::max<int64_t>(1, a.n_items));
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, a);
+  return launched("ransac_kernel<persistent>");
+}
+
+static int check_batched(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
+                         int32_t n_hyp, float thresh, const hg_ransac_tuning *tune, float *best_H,
+                         int32_t *best_count, int32_t *best_hyp, uint8_t *mask, void *ws,
+                         size_t ws_bytes) {
+  HG_REQUIRE(corr && off && best_H && best_count && best_hyp && mask,
+             "hg_ransac_batched: NULL corr, off or output pointer");
+  HG_REQUIRE(n_pairs >= 1, "hg_ransac_batched: n_pairs = %d < 1", n_pairs);
+  HG_REQUIRE(ld >= 1, "hg_ransac_batched: ld < 1");
+  HG_REQUIRE(n_hyp >= 1, "hg_ransac_batched: n_hyp = %d < 1", n_hyp);
+  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f,
+             "hg_ransac_batched: threshold must be finite and > 0");
+  HG_REQUIRE(!tune || tune_valid(*tune), "hg_ransac_batched: unsupported tuning");
+  const size_t need = batched_ws_bytes(n_pairs);
+  if (!ws || ws_bytes < need)
+    return fail(HG_EWORKSPACE, "hg_ransac_batched: workspace of %zu bytes needed, %zu given",
+                need, ws ? ws_bytes : static_cast<size_t>(0));
+  HG_REQUIRE(aligned(ws, 256), "hg_ransac_batched: workspace must be 256-byte aligned");
+  return HG_OK;
+}
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp) {
+  (void)n_pts;
+  if (n_hyp < 1) n_hyp = 1;
+  return std::max(batched_ws_bytes(1), plain_ws_bytes(n_hyp));
+}
+
+extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
+                         float thresh, uint64_t seed, float *best_H, int32_t *best_count,
+                         int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts, void *ws,
+                         size_t ws_bytes, void *stream) {
+  clear_error();
+  if (int st = check_single(corr, n_pts, ld, n_hyp, thresh, best_H, best_count, best_hyp,
+                            inlier_mask, ws, ws_bytes, hg_ransac_ws_bytes(n_pts, n_hyp)))
+    return st;
+  const hipStream_t s = as_stream(stream);
+  // enough workgroups to fill the chip when the hypothesis count allows it
+  const int HB = (n_hyp >= 64 * device_cus()) ? 32 : 16;
+  const int P = 8;
+  RansacArgs a = make_args(corr, ld, nullptr, n_pts, 1, n_hyp, HB, thresh, seed, best_H,
+                           best_count, best_hyp, inlier_mask, hyp_counts);
+  const BatchedWs w = carve_batched(ws, 1);
+  a.keys = w.keys;
+  a.done = w.done;
+  hipLaunchKernelGGL(ransac_prep_kernel, dim3(1), dim3(64), 0, s, a, 0);
+  if (int st = launched("ransac_prep_kernel")) return st;
+  KernelFn k = pick_kernel<false>(P, HB);
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(a.n_items)), dim3(kThreads), 0, s, a);
+  return launched("ransac_kernel<fused>");
+}
+
+extern "C" int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
+                               float thresh, uint64_t seed, float *best_H, int32_t *best_count,
+                               int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts,
+                               void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  if (int st = check_single(corr, n_pts, ld, n_hyp, thresh, best_H, best_count, best_hyp,
+                            inlier_mask, ws, ws_bytes, hg_ransac_ws_bytes(n_pts, n_hyp)))
+    return st;
+  const hipStream_t s = as_stream(stream);
+  constexpr int HB = 16, P = 8;
+  RansacArgs a = make_args(corr, ld, nullptr, n_pts, 1, n_hyp, HB, thresh, seed, best_H,
+                           best_count, best_hyp, inlier_mask, hyp_counts);
+  char *p = static_cast<char *>(ws);
+  float *Hbuf = reinterpret_cast<float *>(p);
+  p += align256(36ull * n_hyp);
+  uint32_t *valid = reinterpret_cast<uint32_t *>(p);
+  p += align256(4ull * n_hyp);
+  int32_t *counts = reinterpret_cast<int32_t *>(p);
+  p += align256(4ull * n_hyp);
+  unsigned long long *key = reinterpret_cast<unsigned long long *>(p);
+  hipLaunchKernelGGL(plain_solve_kernel, dim3((n_hyp + 255) / 256), dim3(256), 0, s, a, Hbuf,
+                     valid);
+  if (int st = launched("plain_solve_kernel")) return st;
+  hipLaunchKernelGGL((plain_score_kernel<P, HB>), dim3((n_hyp + HB - 1) / HB), dim3(kThreads), 0,
+                     s, a, Hbuf, valid, counts);
+  if (int st = launched("plain_score_kernel")) return st;
+  hipLaunchKernelGGL(plain_argmax_kernel, dim3(1), dim3(kThreads), 0, s, counts, n_hyp, key,
+                     hyp_counts);
+  if (int st = launched("plain_argmax_kernel")) return st;
+  const int mb = std::max(1, std::min(1024, (n_pts + kThreads - 1) / kThreads));
+  hipLaunchKernelGGL(plain_mask_kernel, dim3(mb), dim3(kThreads), 0, s, a, Hbuf, key);
+  return launched("plain_mask_kernel");
+}
+
+extern "C" size_t hg_ransac_batched_ws_bytes(int32_t n_pairs, int32_t n_hyp) {
+  (void)n_hyp;
+  return batched_ws_bytes(n_pairs < 1 ? 1 : n_pairs);
+}
+
+extern "C" int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off,
+                                 int32_t n_pairs, int32_t n_hyp, float thresh, uint64_t seed,
+                                 const hg_ransac_tuning *tune, float *best_H, int32_t *best_count,
+                                 int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts,
+                                 void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  if (int st = check_batched(corr, ld, off, n_pairs, n_hyp, thresh, tune, best_H, best_count,
+                             best_hyp, inlier_mask, ws, ws_bytes))
+    return st;
+  const hg_ransac_tuning t = tune ? *tune : lookup_tune(n_pairs, n_hyp);
+  RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp, t.hyps_per_block, thresh, seed,
+                           best_H, best_count, best_hyp, inlier_mask, hyp_counts);
+  return launch_batched(a, t, ws, as_stream(stream));
+}
+
+extern "C" int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *off,
+                                  const int64_t *off_host, int32_t n_pairs, int32_t n_hyp,
+                                  float thresh, uint64_t seed, void *ws, size_t ws_bytes,
+                                  void *stream, hg_ransac_tuning *out) {
+  clear_error();
+  HG_REQUIRE(off_host && out, "hg_ransac_autotune: NULL off_host or out");
+  HG_REQUIRE(n_pairs >= 1, "hg_ransac_autotune: n_pairs < 1");
+  const int64_t total = off_host[n_pairs];
+  HG_REQUIRE(total >= 0 && ld >= total, "hg_ransac_autotune: ld < total points");
+  float *bh = nullptr;
+  int32_t *bc = nullptr, *bi = nullptr;
+  uint8_t *mk = nullptr;
+  // validate with dummy output pointers first (host only)
+  if (int st = check_batched(corr, ld, off, n_pairs, n_hyp, thresh, nullptr,
+                             reinterpret_cast<float *>(1), reinterpret_cast<int32_t *>(1),
+                             reinterpret_cast<int32_t *>(1), reinterpret_cast<uint8_t *>(1), ws,
+                             ws_bytes))
+    return st;
+  const hipStream_t s = as_stream(stream);
+  HG_HIP(hipMalloc(&bh, 36ull * n_pairs));
+  HG_HIP(hipMalloc(&bc, 4ull * n_pairs));
+  HG_HIP(hipMalloc(&bi, 4ull * n_pairs));
+  HG_HIP(hipMalloc(&mk, static_cast<size_t>(std::max<int64_t>(total, 1))));
+  hipEvent_t e0, e1;
+  HG_HIP(hipEventCreate(&e0));
+  HG_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  hg_ransac_tuning best = kDefaultTune;
+  int status = HG_OK;
+  for (int P : {8, 16})
+    for (int HB : {16, 32, 64})
+      for (int bpc : {1, 2, 4}) {
+        const hg_ransac_tuning t = {P, HB, bpc, 0};
+        RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp, HB, thresh, seed, bh, bc, bi,
+                                 mk, nullptr);
+        if ((status = launch_batched(a, t, ws, s)) != HG_OK) goto done;   // warm-up
+        float ms[3];
+        for (int r = 0; r < 3; ++r) {
+          (void)hipEventRecord(e0, s);
+          if ((status = launch_batched(a, t, ws, s)) != HG_OK) goto done;
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            status = fail(HG_EHIP, "autotune: event sync failed");
+            goto done;
+          }
+          (void)hipEventElapsedTime(&ms[r], e0, e1);
+        }
+        std::sort(ms, ms + 3);
+        if (ms[1] < best_ms) {
+          best_ms = ms[1];
+          best = t;
+        }
+      }
+done:
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(bh);
+  (void)hipFree(bc);
+  (void)hipFree(bi);
+  (void)hipFree(mk);
+  if (status != HG_OK) return status;
+  *out = best;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    read_tune_file();
+    g_tune_cache[tune_key(n_pairs, n_hyp)] = best;
+    write_tune_file();
+  }
+  return HG_OK;
+}
+
+struct hg_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" int hg_ransac_batched_graph_create(const float *corr, int64_t ld, const int64_t *off,
+                                              int32_t n_pairs, int32_t n_hyp, float thresh,
+                                              uint64_t seed, const hg_ransac_tuning *tune,
+                                              float *best_H, int32_t *best_count,
+                                              int32_t *best_hyp, uint8_t *inlier_mask,
+                                              int32_t *hyp_counts, void *ws, size_t ws_bytes,
+                                              void *stream, hg_graph **out) {
+  clear_error();
+  HG_REQUIRE(out, "hg_ransac_batched_graph_create: NULL out");
+  *out = nullptr;
+  if (int st = check_batched(corr, ld, off, n_pairs, n_hyp, thresh, tune, best_H, best_count,
+                             best_hyp, inlier_mask, ws, ws_bytes))
+    return st;
+  const hg_ransac_tuning t = tune ? *tune : lookup_tune(n_pairs, n_hyp);
+  RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp, t.hyps_per_block, thresh, seed,
+                           best_H, best_count, best_hyp, inlier_mask, hyp_counts);
+  // let pending work on the caller's stream finish before capturing elsewhere
+  HG_HIP(hipStreamSynchronize(as_stream(stream)));
+  hipStream_t cap;
+  HG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hg_graph *g = new hg_graph{nullptr, nullptr};
+  int st = HG_OK;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    st = fail(HG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  } else {
+    st = launch_batched(a, t, ws, cap);
+    e = hipStreamEndCapture(cap, &g->graph);
+    if (st == HG_OK && e != hipSuccess)
+      st = fail(HG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (st == HG_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(HG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  (void)hipStreamDestroy(cap);
+  if (st != HG_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return HG_OK;
+}
+
+extern "C" int hg_graph_launch(hg_graph *g, void *stream) {
+  clear_error();
+  HG_REQUIRE(g && g->exec, "hg_graph_launch: NULL graph");
+  HG_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+  return HG_OK;
+}
+
+extern "C" void hg_graph_destroy(hg_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}

@@ -55,3 +55,77 @@ def test_solve4_validation(lib):
     # n == 0 is a no-op even with NULL pointers
     assert f(0, None, None, 0, 0, None, None, None) == _abi.HG_OK
     assert f(1, None, None, 0, 0, None, None, None) == _abi.HG_OK
+
+
+def test_ransac_validation(lib):
+    f = lib.hg_ransac
+    ws_need = lib.hg_ransac_ws_bytes(2000, 4096)
+    assert ws_need > 0
+    args = dict(corr=FAKE, n=2000, ld=2000, nh=4096, th=3.0, seed=1, bh=FAKE, bc=FAKE, bi=FAKE,
+                mask=FAKE, hc=None, ws=C.c_void_p(0x100000), wsb=ws_need)
+
+    def call(fn=f, **kw):
+        a = dict(args, **kw)
+        return fn(a["corr"], a["n"], a["ld"], a["nh"], a["th"], a["seed"], a["bh"], a["bc"], a["bi"],
+                  a["mask"], a["hc"], a["ws"], a["wsb"], None)
+
+    for fn in (lib.hg_ransac, lib.hg_ransac_plain):
+        assert call(fn, n=3) == _abi.HG_EINVAL
+        assert call(fn, ld=1999) == _abi.HG_EINVAL
+        assert call(fn, nh=0) == _abi.HG_EINVAL
+        assert call(fn, th=0.0) == _abi.HG_EINVAL
+        assert call(fn, th=float("nan")) == _abi.HG_EINVAL
+        assert call(fn, th=float("inf")) == _abi.HG_EINVAL
+        assert call(fn, corr=None) == _abi.HG_EINVAL
+        assert call(fn, mask=None) == _abi.HG_EINVAL
+        assert call(fn, ws=None) == _abi.HG_EWORKSPACE
+        assert call(fn, wsb=ws_need - 1) == _abi.HG_EWORKSPACE
+        assert call(fn, ws=C.c_void_p(0x100008)) == _abi.HG_EINVAL     # misaligned
+
+
+def test_batched_validation(lib):
+    need = lib.hg_ransac_batched_ws_bytes(512, 1024)
+    ws = C.c_void_p(0x100000)
+
+    def call(tune=None, **kw):
+        a = dict(corr=FAKE, ld=10, off=FAKE, n_pairs=512, n_hyp=1024, th=3.0, bh=FAKE, ws=ws, wsb=need)
+        a.update(kw)
+        return lib.hg_ransac_batched(a["corr"], a["ld"], a["off"], a["n_pairs"], a["n_hyp"], a["th"], 3,
+                                     tune, a["bh"], FAKE, FAKE, FAKE, None, a["ws"], a["wsb"], None)
+
+    assert call(n_pairs=0) == _abi.HG_EINVAL
+    assert call(off=None) == _abi.HG_EINVAL
+    assert call(n_hyp=0) == _abi.HG_EINVAL
+    assert call(th=-1.0) == _abi.HG_EINVAL
+    assert call(bh=None) == _abi.HG_EINVAL
+    assert call(wsb=need - 1) == _abi.HG_EWORKSPACE
+    bad = _abi.Tuning(5, 16, 1, 0)
+    assert call(tune=C.byref(bad)) == _abi.HG_EINVAL
+    bad = _abi.Tuning(8, 48, 1, 0)
+    assert call(tune=C.byref(bad)) == _abi.HG_EINVAL
+    bad = _abi.Tuning(8, 16, 9, 0)
+    assert call(tune=C.byref(bad)) == _abi.HG_EINVAL
+    h = C.c_void_p()
+    assert lib.hg_ransac_batched_graph_create(FAKE, 10, FAKE, 0, 1024, 3.0, 3, None, FAKE, FAKE, FAKE,
+                                              FAKE, None, ws, need, None, C.byref(h)) == _abi.HG_EINVAL
+    assert not h.value
+    assert lib.hg_graph_launch(None, None) == _abi.HG_EINVAL
+    lib.hg_graph_destroy(None)
+
+
+def test_diff_validation(lib):
+    assert lib.hg_aca_rect_fwd(FAKE, -1, 0.0, 0.0, 127.0, 1.0, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_rect_fwd(FAKE, 4, 0.0, 0.0, 0.0, 1.0, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_rect_fwd(FAKE, 4, 0.0, 0.0, 127.0, -1.0, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_rect_fwd(None, 4, 0.0, 0.0, 127.0, 1.0, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_rect_fwd(None, 0, 0.0, 0.0, 127.0, 1.0, None, None) == _abi.HG_OK
+    assert lib.hg_aca_rect_bwd(FAKE, None, 4, 0.0, 0.0, 127.0, 1.0, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_l1_fwd(FAKE, FAKE, FAKE, 4, 0, 128, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_l1_fwd(FAKE, None, FAKE, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_l1_fwd(None, FAKE, FAKE, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_l1_fwd(None, None, None, 0, 128, 128, None, None) == _abi.HG_OK
+    assert lib.hg_warp_l1_bwd(FAKE, FAKE, FAKE, None, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_store_fwd(FAKE, FAKE, 4, 128, 40000, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_l1_fwd(FAKE, FAKE, 4, 128, 128, None, None) == _abi.HG_EINVAL
+    assert lib.hg_l1_bwd(FAKE, FAKE, None, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_bwd_from_grad(FAKE, FAKE, FAKE, 4, 128, 128, None, None) == _abi.HG_EINVAL

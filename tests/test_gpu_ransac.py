@@ -1,0 +1,229 @@
+"""RANSAC on the GPU against the oracle (parity tests).
+
+Bar (integer results): the sampled hypotheses' validity is exact (up to
+samples whose minimum triangle height lies within a relative 1e-3 of the
+degeneracy threshold); every per-hypothesis count lies in the oracle's
+[count_lo, count_hi], i.e. it equals the float64 count except for points whose
+transfer error is within the float32 decision band of the threshold; the
+winning H matches the oracle's within 1e-5 (it is the same float64 ACA, scaled
+and rounded); the mask equals the oracle's inlier set of that H outside the
+band; fused, plain and persistent forms agree bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import homography as hg
+from oracle import ransac as oref
+from tests.gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+TAU = 3.0
+
+
+def to_np(d):
+    return {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in d.items()}
+
+
+def check_pair(corr, n_hyp, seed, got, pair=0, label=""):
+    """Compare one pair's GPU results (numpy dict) with the oracle."""
+    ref = oref.ransac_ref(corr, n_hyp, TAU, seed, pair=pair)
+    idx = ref["idx"]
+    src = np.stack([corr[c, idx[k]] for k in range(4) for c in (0, 1)])
+    dst = np.stack([corr[c, idx[k]] for k in range(4) for c in (2, 3)])
+    mh = hg.min_height(src, dst)
+    borderline = np.abs(mh - hg.DELTA_PX) <= 1e-3 * hg.DELTA_PX
+    counts = got["hyp_counts"].astype(np.int64)
+    valid_o = ref["valid"]
+    # validity: an invalid hypothesis reports 0; compare where not borderline
+    nb = ~borderline
+    gv = counts > 0
+    assert not (gv & ~valid_o & nb).any(), f"{label}: GPU counted an invalid sample"
+    ok = valid_o & nb
+    lo, hi = ref["count_lo"], ref["count_hi"]
+    bad = ok & ((counts < lo) | (counts > hi))
+    assert not bad.any(), (label, np.nonzero(bad)[0][:8], counts[bad][:8], lo[bad][:8], hi[bad][:8])
+    # argmax over the GPU counts, ties to the lowest index
+    bh = int(got["best_hyp"].reshape(-1)[0])
+    bc = int(got["best_count"].reshape(-1)[0])
+    if not valid_o.any():
+        assert bh == -1 and bc == 0 and not got["mask"].any() and not got["best_H"].any()
+        return ref
+    assert bc == counts.max() and bh == int(np.argmax(counts == bc)), label
+    if (lo[valid_o] == hi[valid_o]).all() and not borderline.any():
+        assert bh == ref["best_hyp"] and bc == ref["best_count"], label
+    # best H is the oracle's hypothesis bh (float64 ACA, pow2-scaled, rounded)
+    Hg = got["best_H"].reshape(3, 3)
+    assert hg.herr(Hg, ref["H32"][bh].astype(np.float64)) <= 1e-5, label
+    # mask: the inliers of that H, outside the decision band
+    d = oref.transfer_error(ref["H32"][bh:bh + 1], corr)[0]
+    band = np.maximum(oref.decision_band(ref["H32"][bh:bh + 1], corr, TAU)[0], 1e-4)
+    ex = np.abs(d - TAU) <= band
+    m = got["mask"].astype(bool)
+    assert np.array_equal(m[~ex], (d <= TAU)[~ex]), label
+    assert int(m.sum()) == bc
+    return ref
+
+
+def run_single(corr_np, n_hyp, seed, plain=False, ld=None):
+    import paper_2402_18008_amd as hgpu
+    n = corr_np.shape[1]
+    ld = n if ld is None else ld
+    buf = torch.full((4, ld), float("nan"), device="cuda")
+    buf[:, :n] = torch.from_numpy(corr_np)
+    corr = buf[:, :n]
+    fn = hgpu.hg_ransac_plain if plain else hgpu.hg_ransac
+    out = fn(corr, n_hyp, TAU, seed)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def test_config2_fused_and_plain():
+    require_gpu()
+    cs = synth.config2()
+    announce("ransac fused config2 N=2000 hyps=4096")
+    f = run_single(cs.corr, 4096, 2)
+    announce("ransac plain config2")
+    p = run_single(cs.corr, 4096, 2, plain=True)
+    for k in f:
+        assert np.array_equal(f[k], p[k]), k
+    ref = check_pair(cs.corr, 4096, 2, f, label="config2")
+    recall = (f["mask"].astype(bool) & cs.inlier).sum() / cs.inlier.sum()
+    print("config2 best", int(f["best_count"][0]), "hyp", int(f["best_hyp"][0]), "recall", recall,
+          "oracle best", ref["best_count"])
+    assert recall > 0.6
+    # run-to-run determinism
+    g = run_single(cs.corr, 4096, 2)
+    for k in f:
+        assert np.array_equal(f[k], g[k]), k
+
+
+@pytest.mark.parametrize("n,n_hyp,ld", [(4, 7, 4), (5, 100, 9), (33, 1000, 40), (257, 17, 300),
+                                        (1500, 4097, 1500), (8000, 512, 8003)])
+def test_sizes(n, n_hyp, ld):
+    require_gpu()
+    cs = synth.correspondences(n, 0.5, 1000 + n)
+    announce(f"ransac n={n} hyps={n_hyp} ld={ld}")
+    f = run_single(cs.corr, n_hyp, 77, ld=ld)
+    p = run_single(cs.corr, n_hyp, 77, plain=True, ld=ld)
+    for k in f:
+        assert np.array_equal(f[k], p[k]), k
+    check_pair(cs.corr, n_hyp, 77, f, label=f"n={n}")
+
+
+def test_all_degenerate_and_nonfinite():
+    require_gpu()
+    corr = np.ones((4, 50), np.float32)
+    announce("ransac all-degenerate")
+    for plain in (False, True):
+        f = run_single(corr, 64, 5, plain=plain)
+        assert f["best_hyp"][0] == -1 and f["best_count"][0] == 0
+        assert not f["mask"].any() and not f["best_H"].any() and not f["hyp_counts"].any()
+    # a NaN point: samples containing it are invalid, it is never an inlier
+    cs = synth.correspondences(300, 0.5, 9)
+    corr = cs.corr.copy()
+    corr[2, 5] = np.nan
+    f = run_single(corr, 500, 3)
+    check_pair(corr, 500, 3, f, label="nan")
+    assert f["mask"][5] == 0
+
+
+def test_seed_changes_samples():
+    require_gpu()
+    cs = synth.config2()
+    a = run_single(cs.corr, 256, 1)
+    b = run_single(cs.corr, 256, 2 | (1 << 40))
+    assert not np.array_equal(a["hyp_counts"], b["hyp_counts"])
+    check_pair(cs.corr, 256, 2 | (1 << 40), b, label="seed")
+
+
+# ---- batched ----------------------------------------------------------------
+
+def batched(cb, n_hyp=1024, seed=3, hyp_counts=True):
+    import paper_2402_18008_amd as hgpu
+    corr = torch.from_numpy(cb.corr).cuda()
+    off = torch.from_numpy(cb.off).cuda()
+    return hgpu.BatchedRansac(corr, off, n_hyp, TAU, seed, hyp_counts=hyp_counts)
+
+
+def np_out(br):
+    torch.cuda.synchronize()
+    return dict(best_H=br.best_H.cpu().numpy(), best_count=br.best_count.cpu().numpy(),
+                best_hyp=br.best_hyp.cpu().numpy(), mask=br.mask.cpu().numpy(),
+                hyp_counts=br.hyp_counts.cpu().numpy())
+
+
+def pair_view(cb, out, p):
+    a, b = cb.off[p], cb.off[p + 1]
+    return dict(best_H=out["best_H"][p], best_count=out["best_count"][p:p + 1],
+                best_hyp=out["best_hyp"][p:p + 1], mask=out["mask"][a:b],
+                hyp_counts=out["hyp_counts"][p])
+
+
+def test_batched_small_all_tunings_identical():
+    require_gpu()
+    cb = synth.correspondence_batch(24, 31, n_min=4, n_max=3000)
+    br = batched(cb, n_hyp=300, seed=11)
+    ref = None
+    for P in (8, 16):
+        for HB in (16, 32, 64):
+            for bpc in (1, 2, 4):
+                announce(f"batched 24 pairs tuning P={P} HB={HB} bpc={bpc}")
+                br.run((P, HB, bpc))
+                out = np_out(br)
+                if ref is None:
+                    ref = out
+                else:
+                    for k in ref:
+                        assert np.array_equal(ref[k], out[k]), (k, P, HB, bpc)
+    for p in range(24):
+        check_pair(cb.corr[:, cb.off[p]:cb.off[p + 1]], 300, 11, pair_view(cb, ref, p), pair=p,
+                   label=f"pair {p}")
+
+
+def test_config3_persistent_graph_and_autotune():
+    require_gpu()
+    cb = synth.config3()
+    announce("batched config3 512 pairs x 1024 hyps: direct run")
+    br = batched(cb)
+    br.run()
+    direct = np_out(br)
+    # sampled pairs against the oracle: largest, smallest and a few others
+    ns = np.diff(cb.off)
+    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), 0, 7, 100, 311, 511})
+    for p in pick:
+        check_pair(cb.corr[:, cb.off[p]:cb.off[p + 1]], 1024, 3, pair_view(cb, direct, p), pair=p,
+                   label=f"config3 pair {p}")
+    # every pair: mask count equals best count; best count is the max of its counts
+    for p in range(512):
+        v = pair_view(cb, direct, p)
+        assert int(v["mask"].sum()) == int(v["best_count"][0])
+        assert int(v["best_count"][0]) == int(v["hyp_counts"].max())
+    announce("batched config3 autotune")
+    tune = br.autotune(cb.off)
+    print("autotuned", tune)
+    br.run(tune)
+    out = np_out(br)
+    for k in direct:
+        assert np.array_equal(direct[k], out[k]), k
+    announce("batched config3 graph capture and replays")
+    g = br.graph(tune)
+    for rep in range(3):
+        br.mask.zero_()
+        br.best_count.fill_(-7)
+        torch.cuda.synchronize()
+        g.launch()
+        out = np_out(br)
+        for k in direct:
+            assert np.array_equal(direct[k], out[k]), (k, rep)
+    # change the buffer contents in place; the graph sees the new data
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(cb.corr.shape[1]))
+    br.corr.copy_(br.corr[:, perm.cuda()].clone())
+    torch.cuda.synchronize()
+    g.launch()
+    replay = np_out(br)
+    br.run(tune)
+    again = np_out(br)
+    for k in replay:
+        assert np.array_equal(replay[k], again[k]), k
+    g.close()

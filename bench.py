@@ -256,10 +256,18 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 26, help="quadruples (default 2^26)")
-    ap.add_argument("--solver-only", action="store_true",
-                    help="time the headline solver only (for profiler runs)")
+    ap.add_argument("--part", default="all",
+                    choices=["all", "solver", "ransac", "batched", "diff"],
+                    help="run only one stage (for profiler runs); the JSON line then carries "
+                         "only that stage")
+    ap.add_argument("--solver-only", action="store_true", help="same as --part solver")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="with --part solver: also run a plain 4 GiB device copy (reference "
+                         "for hardware byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.solver_only:
+        args.part = "solver"
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the hot path "
               f"has no multi-GPU form in this build", file=sys.stderr)
@@ -267,6 +275,13 @@ def main():
 
     import numpy as np
     import torch
+
+    stream = torch.cuda.current_stream()
+    if args.part in ("ransac", "batched", "diff"):
+        fn = {"ransac": bench_ransac_single, "batched": bench_ransac_batched,
+              "diff": bench_diff}[args.part]
+        print(json.dumps({"part": args.part, **fn(stream)}), flush=True)
+        return
 
     import synth
     import paper_2402_18008_amd as hgpu
@@ -282,7 +297,6 @@ def main():
     D = torch.from_numpy(dst).to(dev)
     H = torch.empty((9, n), dtype=torch.float32, device=dev)
     F = torch.empty(n, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
     def step():
@@ -317,16 +331,27 @@ def main():
                      "bytes_per_unit": BYTES_PER_QUAD},
     }
     extra = {}
-    if not args.solver_only:
+    if args.part == "solver" and args.with_copy:
+        # copies of the 4 GiB source planes (S.numel() * 4 bytes each way): one with
+        # the solver's access pattern, one by torch; references for byte counters
+        C = torch.empty_like(S)
+        for _ in range(2):
+            hgpu.hg_stream_copy(S, C)
+            torch.neg(S, out=C)
+        torch.cuda.synchronize()
+        extra["copy_bytes_each_way"] = S.numel() * 4
+        del C
+    if args.part == "all":
         # SKS on the same batch
         def sks():
             hgpu.hg_solve4(S, D, hgpu.HG_SKS, H=H, flags=F)
         t, p = time_launches(sks, 20, 3, stream)
         extra["sks_2p26"] = {"homographies_per_s": n / (t / 20 * 1e-3),
                              "GBps": BYTES_PER_QUAD * n / (np.mean(p) * 1e-3) / 1e9}
-        # plain copy of the input planes: the practical streaming ceiling
+        # plain copy of the input planes with the solver's access pattern: the
+        # practical streaming ceiling of that pattern
         C = torch.empty_like(S)
-        t, p = time_launches(lambda: C.copy_(S), 10, 2, stream)
+        t, p = time_launches(lambda: hgpu.hg_stream_copy(S, C), 10, 2, stream)
         extra["copy_ceiling_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
         del C
         # small batch latency: 4096 quadruples

@@ -73,6 +73,13 @@ enum { HG_FLAG_NEAR_DEGENERATE = 1, HG_FLAG_NONFINITE_INPUT = 2, HG_FLAG_ZERO_H 
 int hg_solve4(int method, const float *src, const float *dst, int64_t n, int64_t ld,
               float *H, uint8_t *flags, void *stream);
 
+/* Plain device copy of n floats with the access pattern of hg_solve4 (one
+ * float per lane, 512-thread workgroups, non-temporal loads and stores). Not
+ * part of the method: it is the reference for calibrating hardware byte
+ * counters and the streaming ceiling of that pattern. n == 0 is a no-op;
+ * NULL pointer or n < 0 -> HG_EINVAL.                                       */
+int hg_stream_copy(const float *src, float *dst, int64_t n, void *stream);
+
 /* ---- single-pair RANSAC --------------------------------------------------
  * Hypothesise and verify (RANSAC stage of the experiments): hypothesis j
  * draws 4 distinct correspondences with Philox4x32-10 (key = seed, counter =
@@ -89,8 +96,9 @@ int hg_solve4(int method, const float *src, const float *dst, int64_t n, int64_t
  *               0 for degenerate samples.
  *   ws          device workspace of at least hg_ransac_ws_bytes(...) bytes.
  * hg_ransac is the fused form (sampling, solving and scoring in one kernel,
- * then a mask kernel); hg_ransac_plain runs the same arithmetic as separate
- * kernels (solve all -> H buffer, score, argmax, mask) and returns identical
+ * then one kernel that reduces the per-workgroup winners and writes the
+ * mask); hg_ransac_plain runs the same arithmetic as separate kernels (solve
+ * all -> H buffer, score -> counts, argmax, mask) and returns identical
  * results.                                                                    */
 size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp);
 int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,

@@ -64,6 +64,18 @@ def hg_solve4(src, dst, method=HG_ACA, H=None, flags=None, stream=None):
 solve4 = hg_solve4
 
 
+def hg_stream_copy(src, dst=None, stream=None):
+    """Copy a float32 tensor with the solver's access pattern (reference for
+    byte counters and streaming ceilings)."""
+    _dev(src, "src")
+    if not src.is_contiguous():
+        raise ValueError("src must be contiguous")
+    if dst is None:
+        dst = torch.empty_like(src)
+    _abi.call("hg_stream_copy", src.data_ptr(), dst.data_ptr(), src.numel(), _stream(stream))
+    return dst
+
+
 # ---- RANSAC ----------------------------------------------------------------
 
 def _corr_planes(corr):

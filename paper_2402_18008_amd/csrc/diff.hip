@@ -178,39 +178,94 @@ __device__ __forceinline__ int adjugate_scaled(const double *Hd, double G[9]) {
   return e;
 }
 
-// Bilinear sample with zero padding and its gradient with respect to (sx, sy).
+// Bilinear sampling with zero padding, split into an address stage (all four
+// taps clamped into the image, so every load is in bounds) and an evaluation
+// stage, so that a thread can issue the loads of several pixels before using
+// any of them.
+struct TapAddr {
+  int i00, i01, i10, i11;   // clamped linear indices
+  uint32_t in;              // bit k set when tap k lies inside the image
+  double ax, ay;            // fractional position in the cell
+};
+
+__device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
+  if (!(fabs(sx) < 1.0e6) || !(fabs(sy) < 1.0e6)) {   // far outside or nan: all taps outside
+    sx = -4.0;
+    sy = -4.0;
+  }
+  const double fx = floor(sx), fy = floor(sy);
+  TapAddr t;
+  t.ax = sx - fx;
+  t.ay = sy - fy;
+  const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
+  const bool x0in = ix >= 0 && ix < w, x1in = ix + 1 >= 0 && ix + 1 < w;
+  const bool y0in = iy >= 0 && iy < h, y1in = iy + 1 >= 0 && iy + 1 < h;
+  const int cx0 = min(max(ix, 0), w - 1), cx1 = min(max(ix + 1, 0), w - 1);
+  const int cy0 = min(max(iy, 0), h - 1), cy1 = min(max(iy + 1, 0), h - 1);
+  t.i00 = cy0 * w + cx0;
+  t.i01 = cy0 * w + cx1;
+  t.i10 = cy1 * w + cx0;
+  t.i11 = cy1 * w + cx1;
+  t.in = (y0in && x0in ? 1u : 0u) | (y0in && x1in ? 2u : 0u) | (y1in && x0in ? 4u : 0u) |
+         (y1in && x1in ? 8u : 0u);
+  return t;
+}
+
 struct Tap {
   double v, dvdx, dvdy;
 };
 
 template <bool GRAD>
-__device__ __forceinline__ Tap bilinear(const float *__restrict__ img, int h, int w, double sx,
-                                        double sy) {
-  Tap t = {0.0, 0.0, 0.0};
-  if (!(fabs(sx) < 1.0e6) || !(fabs(sy) < 1.0e6)) return t;   // far outside or nan
-  const double fx = floor(sx), fy = floor(sy);
-  const double ax = sx - fx, ay = sy - fy;
-  const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
-  const bool x0in = ix >= 0 && ix < w, x1in = ix + 1 >= 0 && ix + 1 < w;
-  const bool y0in = iy >= 0 && iy < h, y1in = iy + 1 >= 0 && iy + 1 < h;
-  // clamped addresses keep every load inside the image; out-of-range taps read 0
-  const int cx0 = min(max(ix, 0), w - 1), cx1 = min(max(ix + 1, 0), w - 1);
-  const int cy0 = min(max(iy, 0), h - 1), cy1 = min(max(iy + 1, 0), h - 1);
-  const float L00 = img[cy0 * w + cx0], L01 = img[cy0 * w + cx1];
-  const float L10 = img[cy1 * w + cx0], L11 = img[cy1 * w + cx1];
-  const double I00 = (y0in && x0in) ? static_cast<double>(L00) : 0.0;
-  const double I01 = (y0in && x1in) ? static_cast<double>(L01) : 0.0;
-  const double I10 = (y1in && x0in) ? static_cast<double>(L10) : 0.0;
-  const double I11 = (y1in && x1in) ? static_cast<double>(L11) : 0.0;
-  const double top = fma(ax, I01 - I00, I00);
-  const double bot = fma(ax, I11 - I10, I10);
-  t.v = fma(ay, bot - top, top);
+__device__ __forceinline__ Tap tap_eval(const TapAddr &a, float L00, float L01, float L10,
+                                        float L11) {
+  const double I00 = (a.in & 1u) ? static_cast<double>(L00) : 0.0;
+  const double I01 = (a.in & 2u) ? static_cast<double>(L01) : 0.0;
+  const double I10 = (a.in & 4u) ? static_cast<double>(L10) : 0.0;
+  const double I11 = (a.in & 8u) ? static_cast<double>(L11) : 0.0;
+  const double top = fma(a.ax, I01 - I00, I00);
+  const double bot = fma(a.ax, I11 - I10, I10);
+  Tap t;
+  t.v = fma(a.ay, bot - top, top);
+  t.dvdx = 0.0;
+  t.dvdy = 0.0;
   if (GRAD) {
-    t.dvdx = fma(ay, (I11 - I10) - (I01 - I00), I01 - I00);
+    t.dvdx = fma(a.ay, (I11 - I10) - (I01 - I00), I01 - I00);
     t.dvdy = bot - top;
   }
   return t;
 }
+
+// Pixels per thread per loop iteration (loads of all of them in flight at once).
+constexpr int kUnroll = 4;
+
+// Per-thread pixel walker: pixel i = threadIdx.x + u * kDiffThreads + k *
+// kDiffThreads * kUnroll, with (x, y) advanced incrementally.
+struct PixelWalk {
+  int x[kUnroll], y[kUnroll];
+  int step_x, step_y, w;
+  __device__ __forceinline__ PixelWalk(int w_) : w(w_) {
+    constexpr int kStep = kDiffThreads * kUnroll;
+    step_y = kStep / w;
+    step_x = kStep % w;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = static_cast<int>(threadIdx.x) + u * kDiffThreads;
+      y[u] = i / w;
+      x[u] = i % w;
+    }
+  }
+  __device__ __forceinline__ void advance() {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      x[u] += step_x;
+      y[u] += step_y;
+      if (x[u] >= w) {
+        x[u] -= w;
+        ++y[u];
+      }
+    }
+  }
+};
 
 // Workgroup sum of NV per-thread float partials, in double. Result valid in
 // thread 0.
@@ -255,12 +310,23 @@ __device__ __forceinline__ void load_G(const double *H, double G[9], int &e) {
   e = es;
 }
 
+// 1/q in double: a single-precision reciprocal estimate refined by two
+// Newton steps (relative error ~2^-52, no special-case handling needed since
+// G is power-of-two normalised; q outside the float range gives a non-finite
+// position, which samples as outside the image).
+__device__ __forceinline__ double recip(double q) {
+  double r = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(q)));
+  r = fma(fma(-q, r, 1.0), r, r);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return r;
+}
+
 __device__ __forceinline__ void sample_pos(const double *G, double x, double y, double &sx,
                                            double &sy, double &iq2) {
   const double q0 = fma(G[0], x, fma(G[1], y, G[2]));
   const double q1 = fma(G[3], x, fma(G[4], y, G[5]));
   const double q2 = fma(G[6], x, fma(G[7], y, G[8]));
-  iq2 = 1.0 / q2;
+  iq2 = recip(q2);
   sx = q0 * iq2;
   sy = q1 * iq2;
 }
@@ -277,23 +343,36 @@ __global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__
   double G[9];
   int e;
   load_G(H + 9 * b, G, e);
-  const int64_t P = static_cast<int64_t>(h) * w;
-  const float *I = img + b * P;
+  const int P = h * w;
+  const float *I = img + static_cast<int64_t>(b) * P;
+  const float *T = (MODE == 0) ? tgt + static_cast<int64_t>(b) * P : nullptr;
   double acc[1] = {0.0};
-  int y = static_cast<int>(threadIdx.x) / w, x = static_cast<int>(threadIdx.x) % w;
-  const int step_y = kDiffThreads / w, step_x = kDiffThreads % w;
-  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
-    double sx, sy, iq2;
-    sample_pos(G, static_cast<double>(x), static_cast<double>(y), sx, sy, iq2);
-    const double v = bilinear<false>(I, h, w, sx, sy).v;
-    if (MODE == 2) warped[b * P + i] = static_cast<float>(v);
-    if (MODE == 0) acc[0] += fabs(v - static_cast<double>(tgt[b * P + i]));
-    x += step_x;
-    y += step_y;
-    if (x >= w) {
-      x -= w;
-      ++y;
+  PixelWalk pw(w);
+  for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
+    TapAddr ta[kUnroll];
+    float L[kUnroll][4], tv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      double sx, sy, iq2;
+      sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx, sy, iq2);
+      ta[u] = tap_addr(sx, sy, h, w);
+      L[u][0] = I[ta[u].i00];
+      L[u][1] = I[ta[u].i01];
+      L[u][2] = I[ta[u].i10];
+      L[u][3] = I[ta[u].i11];
+      const int i = min(i0 + u * kDiffThreads, P - 1);
+      if (MODE == 0) tv[u] = T[i];
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = i0 + u * kDiffThreads;
+      if (i < P) {
+        const double v = tap_eval<false>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]).v;
+        if (MODE == 2) warped[static_cast<int64_t>(b) * P + i] = static_cast<float>(v);
+        if (MODE == 0) acc[0] += fabs(v - static_cast<double>(tv[u]));
+      }
+    }
+    pw.advance();
   }
   if (MODE == 0) {
     double s[1];
@@ -334,42 +413,54 @@ __global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
   double G[9];
   int e;
   load_G(H + 9 * b, G, e);
-  const int64_t P = static_cast<int64_t>(h) * w;
-  const float *I = img + b * P;
+  const int P = h * w;
+  const float *I = img + static_cast<int64_t>(b) * P;
+  const float *T = FROM_STORED ? grad_warped + static_cast<int64_t>(b) * P
+                               : tgt + static_cast<int64_t>(b) * P;
   const double gl = FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(P);
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int y = static_cast<int>(threadIdx.x) / w, x = static_cast<int>(threadIdx.x) % w;
-  const int step_y = kDiffThreads / w, step_x = kDiffThreads % w;
-  for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
-    const double xf = static_cast<double>(x), yf = static_cast<double>(y);
-    double sx, sy, iq2;
-    sample_pos(G, xf, yf, sx, sy, iq2);
-    const Tap t = bilinear<true>(I, h, w, sx, sy);
-    double g;
-    if (FROM_STORED) {
-      g = static_cast<double>(grad_warped[b * P + i]);
-    } else {
-      const double r = t.v - static_cast<double>(tgt[b * P + i]);
-      g = (r > 0.0) ? gl : ((r < 0.0) ? -gl : 0.0);
+  PixelWalk pw(w);
+  for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
+    TapAddr ta[kUnroll];
+    double sx[kUnroll], sy[kUnroll], iq2[kUnroll];
+    float L[kUnroll][4], tv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx[u], sy[u],
+                 iq2[u]);
+      ta[u] = tap_addr(sx[u], sy[u], h, w);
+      L[u][0] = I[ta[u].i00];
+      L[u][1] = I[ta[u].i01];
+      L[u][2] = I[ta[u].i10];
+      L[u][3] = I[ta[u].i11];
+      tv[u] = T[min(i0 + u * kDiffThreads, P - 1)];
     }
-    const double gx = g * t.dvdx, gy = g * t.dvdy;
-    const double a0 = gx * iq2, a1 = gy * iq2;
-    const double a2 = -(gx * sx + gy * sy) * iq2;
-    acc[0] = fma(a0, xf, acc[0]);
-    acc[1] = fma(a0, yf, acc[1]);
-    acc[2] += a0;
-    acc[3] = fma(a1, xf, acc[3]);
-    acc[4] = fma(a1, yf, acc[4]);
-    acc[5] += a1;
-    acc[6] = fma(a2, xf, acc[6]);
-    acc[7] = fma(a2, yf, acc[7]);
-    acc[8] += a2;
-    x += step_x;
-    y += step_y;
-    if (x >= w) {
-      x -= w;
-      ++y;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (i0 + u * kDiffThreads >= P) continue;
+      const Tap t = tap_eval<true>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]);
+      double g;
+      if (FROM_STORED) {
+        g = static_cast<double>(tv[u]);
+      } else {
+        const double r = t.v - static_cast<double>(tv[u]);
+        g = (r > 0.0) ? gl : ((r < 0.0) ? -gl : 0.0);
+      }
+      const double xf = static_cast<double>(pw.x[u]), yf = static_cast<double>(pw.y[u]);
+      const double gx = g * t.dvdx, gy = g * t.dvdy;
+      const double a0 = gx * iq2[u], a1 = gy * iq2[u];
+      const double a2 = -(gx * sx[u] + gy * sy[u]) * iq2[u];
+      acc[0] = fma(a0, xf, acc[0]);
+      acc[1] = fma(a0, yf, acc[1]);
+      acc[2] += a0;
+      acc[3] = fma(a1, xf, acc[3]);
+      acc[4] = fma(a1, yf, acc[4]);
+      acc[5] += a1;
+      acc[6] = fma(a2, xf, acc[6]);
+      acc[7] = fma(a2, yf, acc[7]);
+      acc[8] += a2;
     }
+    pw.advance();
   }
   double gG[9];
   block_sum<9>(acc, gG);
@@ -380,6 +471,7 @@ __global__ void l1_fwd_kernel(const float *__restrict__ warped, const float *__r
                               int64_t P, float *__restrict__ loss) {
   const int b = blockIdx.x;
   double acc[1] = {0.0};
+#pragma unroll 4
   for (int64_t i = threadIdx.x; i < P; i += kDiffThreads)
     acc[0] += fabs(static_cast<double>(warped[b * P + i]) - static_cast<double>(tgt[b * P + i]));
   double s[1];
@@ -392,6 +484,7 @@ __global__ void l1_bwd_kernel(const float *__restrict__ warped, const float *__r
                               float *__restrict__ gw) {
   const int b = blockIdx.x;
   const float gl = static_cast<float>(static_cast<double>(grad_loss[b]) / static_cast<double>(P));
+#pragma unroll 4
   for (int64_t i = threadIdx.x; i < P; i += kDiffThreads) {
     const float r = warped[b * P + i] - tgt[b * P + i];
     gw[b * P + i] = (r > 0.0f) ? gl : ((r < 0.0f) ? -gl : 0.0f);

@@ -10,7 +10,8 @@
 // pair's inlier mask and best outputs.
 //
 // Forms:
-//  * fused single pair: grid = hypothesis blocks, plus a small reset kernel;
+//  * fused single pair: grid = hypothesis blocks, each writing its best key;
+//    a second kernel reduces them and writes the mask;
 //  * plain single pair: solve all -> H buffer, score, argmax, mask kernels;
 //  * batched persistent: CUs x blocks_per_cu workgroups drain an atomic queue
 //    of items ordered by pair size (largest first).
@@ -52,6 +53,8 @@ struct RansacArgs {
   uint32_t *done;
   uint32_t *queue;
   const int32_t *order;    // pair processing order (largest first), or nullptr
+  float *hbuf;             // single pair: every hypothesis's H (9 floats), or nullptr
+  unsigned long long *blockbest;   // single pair: best key of each work item, or nullptr
 };
 
 __device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &base, uint32_t &n) {
@@ -66,46 +69,70 @@ __device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &
   }
 }
 
+// Maximum of a 64-bit value over the 64 lanes of a wave (result in every lane).
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
 __device__ __forceinline__ float bcast(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Score hypotheses Hs[0..nh) (LDS, 9 floats each; valid[h] != 0) against the
-// points [base, base + n): per-wave partial counts into part[wave][h].
-template <int P, int HB>
-__device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
-                                           const float (*Hs)[9], const uint32_t *valid, int nh,
-                                           uint32_t (*part)[HB]) {
+// Count, for each hypothesis h < nh whose bit is set in vmask, the inliers
+// among the points [base, base + n) held in registers (P per lane); each wave
+// adds its counts into cnt[h] (LDS atomics). TAIL: the chunk runs past n and
+// lanes beyond it are masked out of the ballots.
+template <int P, bool TAIL>
+__device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
+                                            const float *X2, const float *Y2, uint32_t c0,
+                                            uint32_t n, const float (*Hs)[9], uint64_t vmask,
+                                            int nh, uint32_t *cnt) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
-  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
-  const float nan = __int_as_float(0x7fc00000);
-  for (uint32_t c0 = 0; c0 < n; c0 += kWaves * 64 * P) {
-    float x1[P], y1[P], x2[P], y2[P];
+  float x1[P], y1[P], x2[P], y2[P];
+  uint64_t live[TAIL ? P : 1];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const uint32_t i = c0 + (p * kWaves + wave) * 64 + lane;
+    const uint32_t j = (TAIL && i >= n) ? n - 1u : i;   // every load stays inside the pair
+    x1[p] = X1[j];
+    y1[p] = Y1[j];
+    x2[p] = X2[j];
+    y2[p] = Y2[j];
+    if (TAIL) live[p] = __ballot(i < n);
+  }
+  for (int h = 0; h < nh; ++h) {
+    if (!((vmask >> h) & 1ull)) continue;
+    float hh[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) hh[k] = bcast(Hs[h][k]);
+    uint32_t c = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const uint32_t i = c0 + (p * kWaves + wave) * 64 + lane;
-      const bool in = i < n;
-      const uint32_t j = in ? i : n - 1u;   // every load stays inside the pair
-      const float v0 = X1[j], v1 = Y1[j], v2 = X2[j], v3 = Y2[j];
-      x1[p] = in ? v0 : nan;
-      y1[p] = in ? v1 : nan;
-      x2[p] = in ? v2 : nan;
-      y2[p] = in ? v3 : nan;
+      uint64_t m = __ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p], a.tau));
+      if (TAIL) m &= live[p];
+      c += __popcll(m);
     }
-    for (int h = 0; h < nh; ++h) {
-      if (!__builtin_amdgcn_readfirstlane(valid[h])) continue;
-      float hh[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) hh[k] = bcast(Hs[h][k]);
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-        cnt += __popcll(__ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p], a.tau)));
-      if (lane == 0) part[wave][h] += cnt;
-    }
+    if (lane == 0 && c) atomicAdd(&cnt[h], c);
   }
+}
+
+template <int P>
+__device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
+                                           const float (*Hs)[9], uint64_t vmask, int nh,
+                                           uint32_t *cnt) {
+  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
+  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
+  constexpr uint32_t kChunk = kWaves * 64 * P;
+  uint32_t c0 = 0;
+  for (; c0 + kChunk <= n; c0 += kChunk)
+    score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+  if (c0 < n) score_chunk<P, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
 }
 
 // Shared memory of one workgroup.
@@ -113,7 +140,7 @@ template <int HB>
 struct Smem {
   float H[HB][9];
   uint32_t valid[HB];
-  uint32_t part[kWaves][HB];
+  uint32_t cnt[HB];
   float bestH[9];
   int64_t item;
   uint32_t last;
@@ -128,6 +155,8 @@ __device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n
     sm.key = key;
     if (key != 0ull) {
       const uint32_t hyp = 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
+      // the winner is recomputed (same device function, same bits) rather than read
+      // from another workgroup's memory
       make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, hyp, static_cast<uint32_t>(p),
                       sm.bestH);
       a.best_count[p] = static_cast<int32_t>((key >> 32) - 1ull);
@@ -166,34 +195,51 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   if (threadIdx.x < HB) {
     const int t = threadIdx.x;
     uint32_t f = kZeroH;
-    if (t < nh)
+    if (t < nh) {
       f = make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, static_cast<uint32_t>(h0 + t),
                           static_cast<uint32_t>(p), sm.H[t]);
-    sm.valid[t] = (t < nh && f == 0u) ? 1u : 0u;
-  }
-  for (int i = threadIdx.x; i < kWaves * HB; i += kThreads) sm.part[i / HB][i % HB] = 0u;
-  __syncthreads();
-  // 2. score
-  score_hyps<P, HB>(a, base, n, sm.H, sm.valid, nh, sm.part);
-  __syncthreads();
-  // 3. reduce over waves, publish counts and the argmax key
-  if (threadIdx.x < nh) {
-    const int t = threadIdx.x;
-    uint32_t c = 0;
+      if (a.hbuf)
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += sm.part[w][t];
-    const bool ok = sm.valid[t] != 0u;
-    if (a.hyp_counts)
-      a.hyp_counts[static_cast<int64_t>(p) * a.n_hyp + h0 + t] = ok ? static_cast<int32_t>(c) : 0;
-    if (ok) atomicMax(&a.keys[p], pack_key(c, static_cast<uint32_t>(h0 + t)));
+        for (int k = 0; k < 9; ++k) a.hbuf[9ll * (h0 + t) + k] = sm.H[t][k];
+    }
+    sm.valid[t] = (t < nh && f == 0u) ? 1u : 0u;
+    sm.cnt[t] = 0u;
   }
-  __threadfence();
   __syncthreads();
-  // 4. the last block of this pair writes its mask
-  if (threadIdx.x == 0) sm.last = (atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1));
+  // 2. score (validity as a wave-uniform bit mask)
+  const int lane = threadIdx.x & 63;
+  const uint64_t vmask = __ballot(lane < nh && sm.valid[lane] != 0u);
+  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt);
+  __syncthreads();
+  // 3. publish counts and the block's best key (wave 0 holds all HB <= 64)
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    unsigned long long key = 0ull;
+    if (t < nh) {
+      const uint32_t c = sm.cnt[t];
+      const bool ok = sm.valid[t] != 0u;
+      if (a.hyp_counts)
+        a.hyp_counts[static_cast<int64_t>(p) * a.n_hyp + h0 + t] = ok ? static_cast<int32_t>(c) : 0;
+      if (ok) key = pack_key(c, static_cast<uint32_t>(h0 + t));
+    }
+    key = wave_max_u64(key);
+    if (t == 0) {
+      if (a.blockbest) {
+        a.blockbest[item] = key;     // reduced by the mask kernel
+      } else {
+        if (key != 0ull) atomicMax(&a.keys[p], key);
+        // release this block's results, then count it; the last block of the pair
+        // (all blocks' keys are in) writes the pair's mask
+        __threadfence();
+        sm.last = (atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1));
+      }
+    }
+  }
+  if (a.blockbest) return;
   __syncthreads();
   if (sm.last) {
-    __threadfence();
+    if (threadIdx.x == 0) __threadfence();
+    __syncthreads();
     finish_pair<HB>(a, p, base, n, sm);
   }
   __syncthreads();
@@ -216,31 +262,73 @@ __global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
   }
 }
 
-// Resets keys, done counters and the queue, and ranks pairs by size
-// (largest first, ties by index) when the pair count is small enough for the
-// quadratic ranking.
-__global__ void ransac_prep_kernel(RansacArgs a, int rank) {
+// Single pair, after the fused kernel: reduce the work items' best keys (every
+// workgroup does it redundantly), then write the best outputs (workgroup 0)
+// and this workgroup's slice of the inlier mask.
+__global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
+  __shared__ unsigned long long red[kWaves];
+  __shared__ float bh[9];
+  unsigned long long best = 0ull;
+  for (int64_t j = threadIdx.x; j < a.n_items; j += kThreads) best = max(best, a.blockbest[j]);
+  best = wave_max_u64(best);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  unsigned long long key = 0ull;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) key = max(key, red[w]);
+  const bool any = key != 0ull;
+  const uint32_t hyp = any ? 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull) : 0u;
+  if (threadIdx.x < 9) bh[threadIdx.x] = any ? a.hbuf[9ull * hyp + threadIdx.x] : 0.0f;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < 9) a.best_H[threadIdx.x] = bh[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.best_count[0] = any ? static_cast<int32_t>((key >> 32) - 1ull) : 0;
+    a.best_hyp[0] = any ? static_cast<int32_t>(hyp) : -1;
+  }
+  float hh[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) hh[k] = bh[k];
+  const int n = a.n_single;
+  const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+}
+
+// Resets keys, done counters and the queue, and ranks pairs by size (largest
+// first, ties by index): each thread ranks one pair against all sizes, staged
+// through LDS in tiles of kThreads.
+__global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int rank) {
+  __shared__ uint32_t tile[kThreads];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0 && a.queue) *a.queue = 0u;
-  if (p >= a.n_pairs) return;
-  a.keys[p] = 0ull;
-  a.done[p] = 0u;
+  if (p < a.n_pairs) {
+    a.keys[p] = 0ull;
+    a.done[p] = 0u;
+  }
   if (!a.order) return;
   int32_t *order = const_cast<int32_t *>(a.order);
   if (!rank) {
-    order[p] = p;
+    if (p < a.n_pairs) order[p] = p;
     return;
   }
   int64_t b;
-  uint32_t np;
-  pair_range(a, p, b, np);
+  uint32_t np = 0u;
+  if (p < a.n_pairs) pair_range(a, p, b, np);
   int r = 0;
-  for (int q = 0; q < a.n_pairs; ++q) {
-    uint32_t nq;
-    pair_range(a, q, b, nq);
-    r += (nq > np) || (nq == np && q < p);
+  for (int q0 = 0; q0 < a.n_pairs; q0 += kThreads) {
+    const int q = q0 + threadIdx.x;
+    uint32_t nq = 0u;
+    if (q < a.n_pairs) pair_range(a, q, b, nq);
+    __syncthreads();
+    tile[threadIdx.x] = nq;
+    __syncthreads();
+    const int m = min(kThreads, a.n_pairs - q0);
+    for (int k = 0; k < m; ++k) {
+      const uint32_t v = tile[k];
+      r += (v > np) || (v == np && q0 + k < p);
+    }
   }
-  order[r] = p;
+  if (p < a.n_pairs) order[r] = p;
 }
 
 // ---- plain single-pair form -------------------------------------------------
@@ -262,42 +350,45 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
                                                                int32_t *counts) {
   __shared__ float Hs[HB][9];
   __shared__ uint32_t vs[HB];
-  __shared__ uint32_t part[kWaves][HB];
+  __shared__ uint32_t cnt[HB];
   const int h0 = blockIdx.x * HB;
   const int nh = min(HB, a.n_hyp - h0);
   for (int i = threadIdx.x; i < HB * 9; i += kThreads)
     Hs[i / 9][i % 9] = (i / 9 < nh) ? Hbuf[9 * h0 + i] : 0.0f;
-  for (int i = threadIdx.x; i < HB; i += kThreads) vs[i] = (i < nh) ? valid[h0 + i] : 0u;
-  for (int i = threadIdx.x; i < kWaves * HB; i += kThreads) part[i / HB][i % HB] = 0u;
-  __syncthreads();
-  score_hyps<P, HB>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vs, nh, part);
-  __syncthreads();
-  if (threadIdx.x < nh) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += part[w][threadIdx.x];
-    counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(c) : -1;
+  for (int i = threadIdx.x; i < HB; i += kThreads) {
+    vs[i] = (i < nh) ? valid[h0 + i] : 0u;
+    cnt[i] = 0u;
   }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t vmask = __ballot(lane < nh && vs[lane] != 0u);
+  score_hyps<P>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vmask, nh, cnt);
+  __syncthreads();
+  if (threadIdx.x < nh)
+    counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(cnt[threadIdx.x]) : -1;
 }
 
 // One workgroup: argmax over counts (-1 = invalid), ties to the lower index.
-__global__ __launch_bounds__(kThreads) void plain_argmax_kernel(const int32_t *counts, int n_hyp,
-                                                                unsigned long long *key,
-                                                                int32_t *hyp_counts) {
-  __shared__ unsigned long long red[kThreads];
+constexpr int kArgmaxThreads = 1024;
+__global__ __launch_bounds__(kArgmaxThreads) void plain_argmax_kernel(const int32_t *counts,
+                                                                      int n_hyp,
+                                                                      unsigned long long *key,
+                                                                      int32_t *hyp_counts) {
+  __shared__ unsigned long long red[kArgmaxThreads / 64];
   unsigned long long best = 0ull;
-  for (int j = threadIdx.x; j < n_hyp; j += kThreads) {
+  for (int j = threadIdx.x; j < n_hyp; j += kArgmaxThreads) {
     const int32_t c = counts[j];
     if (hyp_counts) hyp_counts[j] = c < 0 ? 0 : c;
     if (c >= 0) best = max(best, pack_key(static_cast<uint32_t>(c), static_cast<uint32_t>(j)));
   }
-  red[threadIdx.x] = best;
+  best = wave_max_u64(best);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
+  if (threadIdx.x < 64) {
+    unsigned long long v = threadIdx.x < kArgmaxThreads / 64 ? red[threadIdx.x] : 0ull;
+    v = wave_max_u64(v);
+    if (threadIdx.x == 0) *key = v;
   }
-  if (threadIdx.x == 0) *key = red[0];
 }
 
 __global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, const float *Hbuf,
@@ -339,7 +430,8 @@ template <bool PERSISTENT>
 static KernelFn pick_kernel(int P, int HB) {
 #define HG_PICK(PP, HH) \
   if (P == PP && HB == HH) return ransac_kernel<PP, HH, PERSISTENT>;
-  HG_PICK(8, 16) HG_PICK(8, 32) HG_PICK(8, 64) HG_PICK(16, 16) HG_PICK(16, 32) HG_PICK(16, 64)
+  HG_PICK(8, 4) HG_PICK(8, 8) HG_PICK(8, 16) HG_PICK(8, 32) HG_PICK(8, 64)
+  HG_PICK(16, 16) HG_PICK(16, 32) HG_PICK(16, 64)
 #undef HG_PICK
   return nullptr;
 }
@@ -473,6 +565,8 @@ static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, i
   a.done = nullptr;
   a.queue = nullptr;
   a.order = nullptr;
+  a.hbuf = nullptr;
+  a.blockbest = nullptr;
   return a;
 }
 
@@ -485,8 +579,9 @@ static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void 
   a.done = w.done;
   a.queue = w.queue;
   a.order = w.order;
-  const int rank = a.n_pairs <= 16384 ? 1 : 0;
-  hipLaunchKernelGGL(ransac_prep_kernel, dim3((a.n_pairs + 255) / 256), dim3(256), 0, s, a, rank);
+  const int rank = a.n_pairs <= 65536 ? 1 : 0;
+  hipLaunchKernelGGL(ransac_prep_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads),
+                     dim3(kThreads), 0, s, a, rank);
   if (int st = launched("ransac_prep_kernel")) return st;
   KernelFn k = pick_kernel<true>(t.pts_per_lane, t.hyps_per_block);
   if (!k) return fail(HG_EINVAL, "unsupported tuning");
@@ -523,7 +618,10 @@ using namespace hg;
 extern "C" size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp) {
   (void)n_pts;
   if (n_hyp < 1) n_hyp = 1;
-  return std::max(batched_ws_bytes(1), plain_ws_bytes(n_hyp));
+  // fused: every hypothesis's H and each work item's best key (at least 4
+  // hypotheses per item); plain: H buffer, validity, counts and the argmax key
+  return std::max(align256(36ull * n_hyp) + align256(8ull * ((n_hyp + 3) / 4)),
+                  plain_ws_bytes(n_hyp));
 }
 
 extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
@@ -535,19 +633,21 @@ extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n
                             inlier_mask, ws, ws_bytes, hg_ransac_ws_bytes(n_pts, n_hyp)))
     return st;
   const hipStream_t s = as_stream(stream);
-  // enough workgroups to fill the chip when the hypothesis count allows it
-  const int HB = (n_hyp >= 64 * device_cus()) ? 32 : 16;
+  // about two workgroups per compute unit when the hypothesis count allows it
+  int HB = 4;
+  while (HB < 64 && static_cast<int64_t>(HB) * 2 * device_cus() < n_hyp) HB *= 2;
   const int P = 8;
   RansacArgs a = make_args(corr, ld, nullptr, n_pts, 1, n_hyp, HB, thresh, seed, best_H,
                            best_count, best_hyp, inlier_mask, hyp_counts);
-  const BatchedWs w = carve_batched(ws, 1);
-  a.keys = w.keys;
-  a.done = w.done;
-  hipLaunchKernelGGL(ransac_prep_kernel, dim3(1), dim3(64), 0, s, a, 0);
-  if (int st = launched("ransac_prep_kernel")) return st;
+  char *w = static_cast<char *>(ws);
+  a.hbuf = reinterpret_cast<float *>(w);
+  a.blockbest = reinterpret_cast<unsigned long long *>(w + align256(36ull * n_hyp));
   KernelFn k = pick_kernel<false>(P, HB);
   hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(a.n_items)), dim3(kThreads), 0, s, a);
-  return launched("ransac_kernel<fused>");
+  if (int st = launched("ransac_kernel<fused>")) return st;
+  const int mb = std::max(1, std::min(1024, (n_pts + kThreads - 1) / kThreads));
+  hipLaunchKernelGGL(ransac_mask_kernel, dim3(mb), dim3(kThreads), 0, s, a);
+  return launched("ransac_mask_kernel");
 }
 
 extern "C" int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
@@ -576,7 +676,7 @@ extern "C" int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int
   hipLaunchKernelGGL((plain_score_kernel<P, HB>), dim3((n_hyp + HB - 1) / HB), dim3(kThreads), 0,
                      s, a, Hbuf, valid, counts);
   if (int st = launched("plain_score_kernel")) return st;
-  hipLaunchKernelGGL(plain_argmax_kernel, dim3(1), dim3(kThreads), 0, s, counts, n_hyp, key,
+  hipLaunchKernelGGL(plain_argmax_kernel, dim3(1), dim3(kArgmaxThreads), 0, s, counts, n_hyp, key,
                      hyp_counts);
   if (int st = launched("plain_argmax_kernel")) return st;
   const int mb = std::max(1, std::min(1024, (n_pts + kThreads - 1) / kThreads));

@@ -129,3 +129,9 @@ def test_diff_validation(lib):
     assert lib.hg_l1_fwd(FAKE, FAKE, 4, 128, 128, None, None) == _abi.HG_EINVAL
     assert lib.hg_l1_bwd(FAKE, FAKE, None, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
     assert lib.hg_warp_bwd_from_grad(FAKE, FAKE, FAKE, 4, 128, 128, None, None) == _abi.HG_EINVAL
+
+
+def test_stream_copy_validation(lib):
+    assert lib.hg_stream_copy(FAKE, FAKE, -1, None) == _abi.HG_EINVAL
+    assert lib.hg_stream_copy(None, FAKE, 5, None) == _abi.HG_EINVAL
+    assert lib.hg_stream_copy(None, None, 0, None) == _abi.HG_OK

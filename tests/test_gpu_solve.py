@@ -122,3 +122,14 @@ def test_config1_full_size_sampled():
     Hs = H[:, torch.from_numpy(sel).cuda()].cpu().numpy().T.reshape(-1, 3, 3)
     st = check(src[:, sel], dst[:, sel], "aca", Hs, fg[sel], "config1")
     print("config1", st, "flagged", int((fg != 0).sum()))
+
+
+def test_stream_copy():
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    for n in (1, 513, 100003):
+        x = torch.randn(n, device="cuda")
+        announce(f"stream copy n={n}")
+        y = hgpu.hg_stream_copy(x)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)

@@ -103,11 +103,18 @@ def cpu_baseline(src, dst, n_sample, workers):
     jobs = [(a, min(a + chunk, n_sample)) for a in range(0, n_sample, chunk)] * 2
     _CB["src"], _CB["dst"] = src, dst
     ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
+    pool = ctx.Pool(workers)
+    try:
         pool.map(_oracle_chunk, jobs[:workers])          # warm the workers
         t = time.perf_counter()
         cpu_s = sum(pool.map(_oracle_chunk, jobs))
         wall = time.perf_counter() - t
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
     return dict(value=2 * n_sample / wall, unit="homographies/s", cores=workers, kind="oracle",
                 sample=f"float64 NumPy ACA, two passes over the first {n_sample} quadruples of "
                        f"the same workload, {len(jobs)} chunks of 2^20 over {workers} processes "
@@ -265,6 +272,8 @@ def main():
                     help="with --part solver: also run a plain 4 GiB device copy (reference "
                          "for hardware byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="host processes for input generation (fewer under a profiler)")
     args = ap.parse_args()
     if args.solver_only:
         args.part = "solver"
@@ -286,7 +295,7 @@ def main():
     import synth
     import paper_2402_18008_amd as hgpu
 
-    workers = max(1, min(16, os.cpu_count() or 1))
+    workers = max(1, min(args.gen_workers, os.cpu_count() or 1))
     n = args.n
     log(f"generating {n} quadruples with {workers} processes")
     t0 = time.perf_counter()
@@ -348,11 +357,11 @@ def main():
         t, p = time_launches(sks, 20, 3, stream)
         extra["sks_2p26"] = {"homographies_per_s": n / (t / 20 * 1e-3),
                              "GBps": BYTES_PER_QUAD * n / (np.mean(p) * 1e-3) / 1e9}
-        # plain copy of the input planes with the solver's access pattern: the
-        # practical streaming ceiling of that pattern
+        # plain copy of the input planes with the solver's access pattern (one float
+        # per lane), for reference
         C = torch.empty_like(S)
         t, p = time_launches(lambda: hgpu.hg_stream_copy(S, C), 10, 2, stream)
-        extra["copy_ceiling_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
+        extra["stream_copy_same_pattern_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
         del C
         # small batch latency: 4096 quadruples
         for meth, name in ((hgpu.HG_ACA, "aca"), (hgpu.HG_SKS, "sks")):

@@ -88,7 +88,7 @@ int hg_stream_copy(const float *src, float *dst, int64_t n, void *stream);
  * (evaluated division-free in float). Degenerate samples (any flag bit) are
  * skipped. best = largest count, ties to the lowest j.
  *   corr        4 planes x1 y1 x2 y2 of n_pts floats at stride ld (>= n_pts).
- *   n_pts >= 4, n_hyp >= 1, thresh finite and > 0.
+ *   n_pts >= 4, n_hyp >= 1, thresh finite and > 0 with 1/thresh finite in float.
  *   best_H      9 floats (output); zeros if no hypothesis is valid.
  *   best_count, best_hyp  1 int32 each (output); best_hyp = -1 if none valid.
  *   inlier_mask n_pts bytes (output): 1 for inliers of best_H.

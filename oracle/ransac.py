@@ -66,18 +66,23 @@ def transfer_error(H, corr):
 
 def decision_band(H, corr, tau):
     """Per (hypothesis, point) bound, in px of transfer error, on how far a
-    float32 evaluation of the division-free test ru^2 + rv^2 <= tau^2 w^2 (with
-    u, v, w = H (x1, y1, 1), ru = u - x2 w, rv = v - y2 w, H entries possibly
-    one float32 ulp off) can move the decision.
+    float32 evaluation of the division-free inlier test can move the decision.
 
-    Each 3-term dot product in float32 (two fused or separate roundings) plus a
-    one-ulp perturbation of every H entry errs by at most 4u times the sum of
-    the magnitudes of its terms (u = 2^-24); the residual adds one rounding and
-    |x2| times the error of w. Propagating to e = ru^2 + rv^2 - tau^2 w^2 (three
-    more roundings on each square) bounds the error of e; since
-    e = w^2 (dist^2 - tau^2) = w^2 (dist - tau)(dist + tau), the decision can
-    only flip if |dist - tau| <= |error of e| / (w^2 (dist + tau)). That bound
-    is returned, doubled for safety."""
+    The evaluation bounded here: with c = 1/tau rounded to float, rows 1-2 of
+    H and the target point are multiplied by c (each product rounded), then
+    u', v', w from 3-term dot products, ru' = u' - (c x2) w, rv' likewise, and
+    inlier iff ru'^2 + rv'^2 <= w^2 -- in exact arithmetic the same test as
+    ||pi(H x1) - x2|| <= tau. The H entries may also be one float32 ulp off.
+
+    Each 3-term dot product (two fused or separate roundings, one-ulp
+    perturbation of every H entry, the rounding of c h) errs by at most 4u
+    times the sum of the magnitudes of its terms (u = 2^-24); the residual
+    adds one rounding and the rounding of c x2 (u |x2 w| each). Propagating to
+    e = ru^2 + rv^2 - tau^2 w^2 (three more roundings on each square) bounds
+    the error of e; since e = w^2 (dist - tau)(dist + tau), the decision can
+    only flip if |dist - tau| <= |error of e| / (w^2 (dist + tau)). The
+    rounding of c moves the effective threshold by at most 2u tau. The sum is
+    returned, doubled for safety."""
     Hs = np.asarray(H, np.float64)
     H = np.abs(Hs)
     x1, y1, x2, y2 = (np.asarray(c, np.float64) for c in corr)
@@ -91,15 +96,15 @@ def decision_band(H, corr, tau):
     ru = u - x2 * w
     rv = v - y2 * w
     Ew = 4 * U32 * Sw
-    Eru = 4 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + ax2 * np.abs(w))
-    Erv = 4 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + ay2 * np.abs(w))
+    Eru = 4 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + 2 * ax2 * np.abs(w))
+    Erv = 4 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + 2 * ay2 * np.abs(w))
     d = ru * ru + rv * rv
     t = tau * tau * w * w
     Ee = (2 * np.abs(ru) * Eru + Eru ** 2 + 2 * np.abs(rv) * Erv + Erv ** 2 + 3 * U32 * d
           + tau * tau * (2 * np.abs(w) * Ew + Ew ** 2) + 3 * U32 * t)
     with np.errstate(divide="ignore", invalid="ignore"):
         dist = np.sqrt(d) / np.abs(w)
-        band = 2.0 * Ee / (w * w * (dist + tau))
+        band = 2.0 * (Ee / (w * w * (dist + tau)) + 2 * U32 * tau)
     return np.where(w == 0, np.inf, band)
 
 

@@ -43,6 +43,7 @@ struct RansacArgs {
   int32_t n_hb;            // hypothesis blocks per pair
   int64_t n_items;         // n_pairs * n_hb
   float tau;
+  float inv_tau;           // 1/tau rounded to float (the scoring form's scale)
   uint32_t k0, k1;         // Philox key (seed low / high word)
   float *best_H;
   int32_t *best_count;
@@ -102,8 +103,8 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
     const uint32_t j = (TAIL && i >= n) ? n - 1u : i;   // every load stays inside the pair
     x1[p] = X1[j];
     y1[p] = Y1[j];
-    x2[p] = X2[j];
-    y2[p] = Y2[j];
+    x2[p] = X2[j] * a.inv_tau;
+    y2[p] = Y2[j] * a.inv_tau;
     if (TAIL) live[p] = __ballot(i < n);
   }
   for (int h = 0; h < nh; ++h) {
@@ -114,7 +115,7 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
     uint32_t c = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      uint64_t m = __ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p], a.tau));
+      uint64_t m = __ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p]));
       if (TAIL) m &= live[p];
       c += __popcll(m);
     }
@@ -138,7 +139,7 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
 // Shared memory of one workgroup.
 template <int HB>
 struct Smem {
-  float H[HB][9];
+  float H[HB][9];          // scoring form (rows 1-2 scaled by 1/tau)
   uint32_t valid[HB];
   uint32_t cnt[HB];
   float bestH[9];
@@ -172,12 +173,12 @@ __device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n
   if (threadIdx.x < 9) a.best_H[9 * p + threadIdx.x] = sm.bestH[threadIdx.x];
   const bool any = sm.key != 0ull;
   float hh[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) hh[k] = sm.bestH[k];
+  score_form(sm.bestH, a.inv_tau, hh);
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   for (uint32_t i = threadIdx.x; i < n; i += kThreads)
-    a.mask[base + i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+    a.mask[base + i] =
+        (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
 }
 
 // Process one work item: pair rank r, hypothesis block hb.
@@ -196,11 +197,13 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
     const int t = threadIdx.x;
     uint32_t f = kZeroH;
     if (t < nh) {
+      float h[9];
       f = make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, static_cast<uint32_t>(h0 + t),
-                          static_cast<uint32_t>(p), sm.H[t]);
+                          static_cast<uint32_t>(p), h);
+      score_form(h, a.inv_tau, sm.H[t]);
       if (a.hbuf)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) a.hbuf[9ll * (h0 + t) + k] = sm.H[t][k];
+        for (int k = 0; k < 9; ++k) a.hbuf[9ll * (h0 + t) + k] = h[k];
     }
     sm.valid[t] = (t < nh && f == 0u) ? 1u : 0u;
     sm.cnt[t] = 0u;
@@ -286,12 +289,11 @@ __global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
     a.best_hyp[0] = any ? static_cast<int32_t>(hyp) : -1;
   }
   float hh[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) hh[k] = bh[k];
+  score_form(bh, a.inv_tau, hh);
   const int n = a.n_single;
   const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
 }
 
 // Resets keys, done counters and the queue, and ranks pairs by size (largest
@@ -353,8 +355,10 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
   __shared__ uint32_t cnt[HB];
   const int h0 = blockIdx.x * HB;
   const int nh = min(HB, a.n_hyp - h0);
-  for (int i = threadIdx.x; i < HB * 9; i += kThreads)
-    Hs[i / 9][i % 9] = (i / 9 < nh) ? Hbuf[9 * h0 + i] : 0.0f;
+  for (int i = threadIdx.x; i < HB * 9; i += kThreads) {
+    const float v = (i / 9 < nh) ? Hbuf[9 * h0 + i] : 0.0f;
+    Hs[i / 9][i % 9] = (i % 9 < 6) ? v * a.inv_tau : v;   // scoring form
+  }
   for (int i = threadIdx.x; i < HB; i += kThreads) {
     vs[i] = (i < nh) ? valid[h0 + i] : 0u;
     cnt[i] = 0u;
@@ -396,10 +400,11 @@ __global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, cons
   const unsigned long long k = *key;
   const bool any = k != 0ull;
   const uint32_t hyp = any ? 0xFFFFFFFFu - static_cast<uint32_t>(k & 0xFFFFFFFFull) : 0u;
-  float hh[9];
+  float bh[9], hh[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) hh[i] = any ? Hbuf[9 * hyp + i] : 0.0f;
-  if (blockIdx.x == 0 && threadIdx.x < 9) a.best_H[threadIdx.x] = hh[threadIdx.x];
+  for (int i = 0; i < 9; ++i) bh[i] = any ? Hbuf[9 * hyp + i] : 0.0f;
+  score_form(bh, a.inv_tau, hh);
+  if (blockIdx.x == 0 && threadIdx.x < 9) a.best_H[threadIdx.x] = bh[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.best_count[0] = any ? static_cast<int32_t>((k >> 32) - 1ull) : 0;
     a.best_hyp[0] = any ? static_cast<int32_t>(hyp) : -1;
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, cons
   const int n = a.n_single;
   const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
+    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
 }
 
 // ---- tuning --------------------------------------------------------------
@@ -532,7 +537,8 @@ static int check_single(const float *corr, int32_t n_pts, int64_t ld, int32_t n_
   HG_REQUIRE(n_pts >= 4, "hg_ransac: n_pts = %d < 4", n_pts);
   HG_REQUIRE(ld >= n_pts, "hg_ransac: ld < n_pts");
   HG_REQUIRE(n_hyp >= 1, "hg_ransac: n_hyp = %d < 1", n_hyp);
-  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f, "hg_ransac: threshold must be finite and > 0");
+  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f && std::isfinite(1.0f / thresh),
+             "hg_ransac: threshold must be finite and > 0 (and 1/threshold finite)");
   if (!ws || ws_bytes < need)
     return fail(HG_EWORKSPACE, "hg_ransac: workspace of %zu bytes needed, %zu given", need,
                 ws ? ws_bytes : static_cast<size_t>(0));
@@ -554,6 +560,7 @@ static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, i
   a.n_hb = (n_hyp + HB - 1) / HB;
   a.n_items = static_cast<int64_t>(n_pairs) * a.n_hb;
   a.tau = thresh;
+  a.inv_tau = 1.0f / thresh;
   a.k0 = static_cast<uint32_t>(seed & 0xFFFFFFFFull);
   a.k1 = static_cast<uint32_t>(seed >> 32);
   a.best_H = best_H;
@@ -600,8 +607,8 @@ static int check_batched(const float *corr, int64_t ld, const int64_t *off, int3
   HG_REQUIRE(n_pairs >= 1, "hg_ransac_batched: n_pairs = %d < 1", n_pairs);
   HG_REQUIRE(ld >= 1, "hg_ransac_batched: ld < 1");
   HG_REQUIRE(n_hyp >= 1, "hg_ransac_batched: n_hyp = %d < 1", n_hyp);
-  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f,
-             "hg_ransac_batched: threshold must be finite and > 0");
+  HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f && std::isfinite(1.0f / thresh),
+             "hg_ransac_batched: threshold must be finite and > 0 (and 1/threshold finite)");
   HG_REQUIRE(!tune || tune_valid(*tune), "hg_ransac_batched: unsupported tuning");
   const size_t need = batched_ws_bytes(n_pairs);
   if (!ws || ws_bytes < need)

@@ -163,14 +163,29 @@ def quadruples_parallel(n, seed, degenerate_every=0, workers=8, out=None):
     lab = np.empty(n, np.uint8)
     nchunks = (n + CHUNK - 1) // CHUNK
     jobs = [(seed, c, min(CHUNK, n - c * CHUNK), degenerate_every, c * CHUNK) for c in range(nchunks)]
+    if workers <= 1 or nchunks <= 1:
+        for job in jobs:
+            c, (s, d, l) = _quad_worker(job)
+            lo = c * CHUNK
+            src[:, lo:lo + s.shape[1]] = s
+            dst[:, lo:lo + s.shape[1]] = d
+            lab[lo:lo + s.shape[1]] = l
+        return src, dst, lab
     ctx = mp.get_context("fork")
-    with ctx.Pool(max(1, min(workers, nchunks))) as pool:
+    pool = ctx.Pool(max(1, min(workers, nchunks)))
+    try:
         for c, (s, d, l) in pool.imap_unordered(_quad_worker, jobs):
             lo = c * CHUNK
             m = s.shape[1]
             src[:, lo:lo + m] = s
             dst[:, lo:lo + m] = d
             lab[lo:lo + m] = l
+        pool.close()      # let the workers exit on their own (no terminate signal)
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
     return src, dst, lab
 
 

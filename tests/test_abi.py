@@ -76,6 +76,7 @@ def test_ransac_validation(lib):
         assert call(fn, th=0.0) == _abi.HG_EINVAL
         assert call(fn, th=float("nan")) == _abi.HG_EINVAL
         assert call(fn, th=float("inf")) == _abi.HG_EINVAL
+        assert call(fn, th=1e-39) == _abi.HG_EINVAL
         assert call(fn, corr=None) == _abi.HG_EINVAL
         assert call(fn, mask=None) == _abi.HG_EINVAL
         assert call(fn, ws=None) == _abi.HG_EWORKSPACE

@@ -73,15 +73,21 @@ def test_hypothesis_h_is_aca_of_sample():
 
 
 def _fp32_division_free(H, corr, tau, fused):
-    """float32 evaluation of ru^2 + rv^2 <= tau^2 w^2 (emulation, test only)."""
-    H = H.astype(np.float32)
-    x1, y1, x2, y2 = (c.astype(np.float32)[None] for c in corr)
+    """float32 evaluation of the scaled division-free test (emulation, test
+    only): rows 1-2 of H and the target point times c = 1/tau,
+    ru'^2 + rv'^2 <= w^2."""
     f32 = np.float32
+    c = f32(1.0) / f32(tau)
+    H = H.astype(f32).copy()
+    H[:, :2, :] = H[:, :2, :] * c
+    x1, y1, x2, y2 = (cc.astype(f32)[None] for cc in corr)
+    x2 = x2 * c
+    y2 = y2 * c
 
-    def fma(a, b, c):
+    def fma(a, b, cc):
         if fused:   # product exact in float64, sum rounded there, then to float32
-            return (a.astype(np.float64) * b + c).astype(f32)
-        return (a * b + c).astype(f32)
+            return (a.astype(np.float64) * b + cc).astype(f32)
+        return (a * b + cc).astype(f32)
 
     def row(i):
         return fma(H[:, i, 0, None], x1, fma(H[:, i, 1, None], y1, H[:, i, 2, None]))
@@ -90,8 +96,7 @@ def _fp32_division_free(H, corr, tau, fused):
     ru = fma(-x2, w, u)
     rv = fma(-y2, w, v)
     d = fma(rv, rv, ru * ru)
-    tw = f32(tau) * w
-    return d <= tw * tw
+    return d <= w * w
 
 
 @pytest.mark.parametrize("fused", [False, True])

@@ -121,7 +121,9 @@ def cpu_baseline(src, dst, n_sample, workers):
                        f"({cpu_s:.1f} s of CPU time, {wall:.2f} s wall)")
 
 
-FP32_FLOP_PER_HYP_PT = 21   # 3 rows x 2 FMA, 2 FMA residuals, mul + FMA norm, 2 mul (tau w)^2
+FP32_FLOP_PER_HYP_PT = 21   # the division-free test as 21 FLOP (FMA = 2): 3 rows x 2 FMA,
+                            # 2 FMA residuals, mul + FMA norm, (tau w)^2; the kernel folds
+                            # tau into the operands and issues 12 VALU instructions
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -200,6 +202,11 @@ def bench_ransac_batched(stream):
             raise RuntimeError("hg_ransac failed in the per-pair loop")
     t, p = time_launches(loop, 5, 1, stream)
     ms_plain = float(np.median(p))
+    # adaptive termination (99 % confidence, cap 1024) on the same pairs
+    ar = hgpu.AdaptiveRansac(corr, off, nh, 3.0, 3, confidence=0.99)
+    t, p = time_launches(lambda: ar.run((tune[0], 64, tune[2])), 20, 3, stream)
+    ms_adaptive = float(np.median(p))
+    n_eval = ar.n_evaluated.cpu().numpy()
     rate = hyp_pts / (ms_graph * 1e-3)
     return {"ransac_batched_512x1024": {
         "hyp_pts": hyp_pts, "tuning": list(tune),
@@ -207,7 +214,9 @@ def bench_ransac_batched(stream):
         "plain_host_loop_ms": ms_plain, "hyp_pts_per_s": rate,
         "speedup_vs_plain": ms_plain / ms_graph,
         "fp32_tflops": FP32_FLOP_PER_HYP_PT * rate / 1e12,
-        "fp32_frac_of_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_PEAK_TFLOPS}}
+        "fp32_frac_of_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_PEAK_TFLOPS,
+        "adaptive_ms": ms_adaptive, "adaptive_mean_hyps_evaluated": float(n_eval.mean()),
+        "adaptive_hyp_pts": float((np.diff(cb.off) * n_eval).sum())}}
 
 
 def bench_diff(stream):

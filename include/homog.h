@@ -137,6 +137,24 @@ int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t
                       uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* Adaptive termination (the RANSAC loop rule of the experiments): each pair
+ * evaluates its hypotheses in rounds of 64 in index order and stops after the
+ * first round at which, with eps = best count / N_p and m hypotheses
+ * evaluated, (1 - eps^4)^m <= 1 - confidence (i.e. m >= log(1 - confidence) /
+ * log(1 - eps^4)), or when m reaches n_hyp_max (the cap). The result is the
+ * best hypothesis among the m evaluated; n_evaluated[p] = m. Rounds of all
+ * pairs run in one persistent launch, round-major; rounds started before a
+ * pair's stopping point was known are discarded, so results do not depend on
+ * timing. Same arguments as hg_ransac_batched otherwise (no per-hypothesis
+ * counts); 0 < confidence < 1; tune->hyps_per_block is ignored (64).
+ * ws >= hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max) bytes.               */
+size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max);
+int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
+                       int32_t n_hyp_max, float thresh, uint64_t seed, double confidence,
+                       const hg_ransac_tuning *tune, float *best_H, int32_t *best_count,
+                       int32_t *best_hyp, uint8_t *inlier_mask, int32_t *n_evaluated, void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* Times every supported tuning on the given problem (allocates temporary
  * outputs, synchronises the stream) and stores the fastest in *out and in the
  * process-wide cache used when tune == NULL; also written to the JSON file

@@ -160,3 +160,52 @@ def brute_force_counts(corr, tau):
             continue
         res[sub] = int((transfer_error(H[None], corr)[0] <= tau).sum())
     return res
+
+
+# ---------------------------------------------------------------------------
+# Adaptive termination (the RANSAC loop rule of the experiments: as many
+# iterations as give, with probability `conf`, at least one all-inlier sample
+# for the best inlier ratio found so far, capped at a maximum).
+
+def required_iterations(eps, conf=0.99):
+    """k = ceil(log(1 - conf) / log(1 - eps^4)): iterations needed for an
+    all-inlier 4-sample with probability conf at inlier ratio eps."""
+    import math
+    if eps >= 1.0:
+        return 1
+    if eps <= 0.0:
+        return math.inf
+    return math.ceil(math.log(1.0 - conf) / math.log1p(-eps ** 4))
+
+
+def ransac_adaptive_ref(corr, n_hyp_max, tau, seed, pair=0, conf=0.99, round_size=64,
+                        band_px=1e-4):
+    """Adaptive single-pair reference. Hypotheses are evaluated in rounds of
+    ``round_size`` (in index order); after each round the best so far gives
+    eps = best_count / N, and the loop stops once the number evaluated m
+    reaches min(required_iterations(eps), n_hyp_max). Returns the ransac_ref
+    dict restricted to the evaluated prefix plus n_eval."""
+    full = ransac_ref(corr, n_hyp_max, tau, seed, pair=pair, band_px=band_px)
+    n = np.asarray(corr).shape[1]
+    valid, counts = full["valid"], full["counts"]
+    m = 0
+    for r in range((n_hyp_max + round_size - 1) // round_size):
+        m = min((r + 1) * round_size, n_hyp_max)
+        c = np.where(valid[:m], counts[:m], -1)
+        best_count = int(c.max()) if valid[:m].any() else 0
+        if m >= min(required_iterations(best_count / n, conf), n_hyp_max):
+            break
+    out = dict(full)
+    out["n_eval"] = m
+    v = valid[:m]
+    if v.any():
+        c = np.where(v, counts[:m], -1)
+        best = int(np.argmax(c))
+        d = transfer_error(full["H32"][best:best + 1], corr)[0]
+        bandv = np.maximum(decision_band(full["H32"][best:best + 1], corr, tau)[0], band_px)
+        out.update(best_hyp=best, best_count=int(counts[best]), best_H=full["H32"][best].copy(),
+                   mask=(d <= tau).astype(np.uint8), mask_exempt=np.abs(d - tau) <= bandv)
+    else:
+        out.update(best_hyp=-1, best_count=0, best_H=np.zeros((3, 3), np.float32),
+                   mask=np.zeros(n, np.uint8), mask_exempt=np.zeros(n, bool))
+    return out

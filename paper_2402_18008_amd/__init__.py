@@ -192,6 +192,39 @@ class BatchedRansac:
         return RansacGraph(self, tune, stream)
 
 
+class AdaptiveRansac:
+    """RANSAC over many uneven pairs with adaptive termination
+    (hg_ransac_adaptive): ``corr`` (4, total) float32, ``off`` (n_pairs + 1,)
+    int64 on the device; outputs best_H (n_pairs, 9), best_count, best_hyp,
+    n_evaluated (n_pairs,) and mask (total,)."""
+
+    def __init__(self, corr, off, n_hyp_max, thresh, seed, confidence=0.99):
+        self.ld, self.total = _corr_planes(corr)
+        _dev(off, "off", torch.int64)
+        self.corr, self.off = corr, off
+        self.n_pairs = off.numel() - 1
+        self.n_hyp, self.thresh = int(n_hyp_max), float(thresh)
+        self.seed, self.confidence = int(seed) & (2**64 - 1), float(confidence)
+        dev = corr.device
+        nb = int(_abi.lib().hg_ransac_adaptive_ws_bytes(self.n_pairs, self.n_hyp))
+        self.ws = _ws(nb, dev, None)
+        self.best_H = torch.empty((self.n_pairs, 9), dtype=torch.float32, device=dev)
+        self.best_count = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        self.best_hyp = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        self.n_evaluated = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        self.mask = torch.empty(self.total, dtype=torch.uint8, device=dev)
+
+    def run(self, tune=None, stream=None):
+        t = _tuning(tune)
+        _abi.call("hg_ransac_adaptive", self.corr.data_ptr(), self.ld, self.off.data_ptr(),
+                  self.n_pairs, self.n_hyp, self.thresh, self.seed, self.confidence,
+                  None if t is None else C.byref(t), self.best_H.data_ptr(),
+                  self.best_count.data_ptr(), self.best_hyp.data_ptr(), self.mask.data_ptr(),
+                  self.n_evaluated.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                  _stream(stream))
+        return self
+
+
 class RansacGraph:
     def __init__(self, br, tune=None, stream=None):
         t = _tuning(tune)

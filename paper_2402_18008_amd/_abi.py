@@ -41,6 +41,9 @@ SIGNATURES = {
     "hg_ransac_batched_ws_bytes": (sz, [i32, i32]),
     "hg_ransac_batched": (C.c_int, [vp, i64, vp, i32, i32, f32, u64, C.POINTER(Tuning),
                                     vp, vp, vp, vp, vp, vp, sz, vp]),
+    "hg_ransac_adaptive_ws_bytes": (sz, [i32, i32]),
+    "hg_ransac_adaptive": (C.c_int, [vp, i64, vp, i32, i32, f32, u64, C.c_double,
+                                     C.POINTER(Tuning), vp, vp, vp, vp, vp, vp, sz, vp]),
     "hg_ransac_autotune": (C.c_int, [vp, i64, vp, vp, i32, i32, f32, u64, vp, sz, vp,
                                      C.POINTER(Tuning)]),
     "hg_ransac_batched_graph_create": (C.c_int, [vp, i64, vp, i32, i32, f32, u64,

@@ -56,6 +56,23 @@ struct RansacArgs {
   const int32_t *order;    // pair processing order (largest first), or nullptr
   float *hbuf;             // single pair: every hypothesis's H (9 floats), or nullptr
   unsigned long long *blockbest;   // single pair: best key of each work item, or nullptr
+  // adaptive termination (nullptr pst = off): work items are rounds of HB
+  // hypotheses in round-major order; per pair and round the round's best key
+  // and a completion flag; per pair the merged-prefix state
+  struct PairState *pst;
+  unsigned long long *rkey;
+  uint32_t *rdone;
+  int32_t *n_eval;
+  double one_minus_conf;
+};
+
+// Merged-prefix state of one pair under adaptive termination. `front` rounds
+// have been merged into `best`; `stop` is the number of rounds after which the
+// stopping rule holds (initially all rounds); only the holder of `lock` reads
+// or writes front, best and finished.
+struct PairState {
+  unsigned long long best;
+  uint32_t front, stop, lock, finished;
 };
 
 __device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &base, uint32_t &n) {
@@ -136,6 +153,74 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
   if (c0 < n) score_chunk<P, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
 }
 
+// Adaptive stopping rule: with eps = best_count / n, enough samples have been
+// drawn once (1 - eps^4)^m <= 1 - confidence, i.e. m >= log(1 - confidence) /
+// log(1 - eps^4) rounded up (m integer). The power is taken by repeated
+// squaring in double.
+__device__ __forceinline__ bool enough_samples(uint32_t best_count, uint32_t n, uint32_t m,
+                                               double one_minus_conf) {
+  if (n == 0u) return false;
+  const double eps = static_cast<double>(best_count) / static_cast<double>(n);
+  const double e2 = eps * eps;
+  const double q = 1.0 - e2 * e2;
+  double r = 1.0, b = q;
+  for (uint32_t e = m; e; e >>= 1) {
+    if (e & 1u) r *= b;
+    b *= b;
+  }
+  return r <= one_minus_conf;
+}
+
+#define HG_AGENT __HIP_MEMORY_SCOPE_AGENT
+
+// Called by one thread after its round's key is published: merges completed
+// rounds in order (under the pair's lock) and applies the stopping rule.
+// Returns true for exactly one caller per pair: the one whose merge reached the
+// stopping round; it receives the final key and the number of hypotheses
+// evaluated. A caller that finds the lock taken leaves: the holder re-checks
+// for newly completed rounds after releasing it.
+__device__ bool adaptive_advance(const RansacArgs &a, int p, uint32_t n_pts, int HB,
+                                 unsigned long long &key_out, int32_t &neval_out) {
+  PairState *st = a.pst + p;
+  const uint32_t nr = static_cast<uint32_t>(a.n_hb);
+  unsigned long long *rkey = a.rkey + static_cast<int64_t>(p) * nr;
+  uint32_t *rdone = a.rdone + static_cast<int64_t>(p) * nr;
+  for (;;) {
+    uint32_t expected = 0u;
+    if (!__hip_atomic_compare_exchange_strong(&st->lock, &expected, 1u, __ATOMIC_SEQ_CST,
+                                              __ATOMIC_SEQ_CST, HG_AGENT))
+      return false;
+    uint32_t f = __hip_atomic_load(&st->front, __ATOMIC_RELAXED, HG_AGENT);
+    uint32_t s = __hip_atomic_load(&st->stop, __ATOMIC_RELAXED, HG_AGENT);
+    unsigned long long best = __hip_atomic_load(&st->best, __ATOMIC_RELAXED, HG_AGENT);
+    const uint32_t finished = __hip_atomic_load(&st->finished, __ATOMIC_RELAXED, HG_AGENT);
+    while (f < s && __hip_atomic_load(&rdone[f], __ATOMIC_SEQ_CST, HG_AGENT) != 0u) {
+      const unsigned long long k = __hip_atomic_load(&rkey[f], __ATOMIC_RELAXED, HG_AGENT);
+      best = k > best ? k : best;
+      ++f;
+      const uint32_t m = min(f * static_cast<uint32_t>(HB), static_cast<uint32_t>(a.n_hyp));
+      const uint32_t bc = best ? static_cast<uint32_t>((best >> 32) - 1ull) : 0u;
+      if (m >= static_cast<uint32_t>(a.n_hyp) || enough_samples(bc, n_pts, m, a.one_minus_conf)) {
+        s = f;
+        __hip_atomic_store(&st->stop, s, __ATOMIC_RELAXED, HG_AGENT);
+      }
+    }
+    __hip_atomic_store(&st->front, f, __ATOMIC_RELAXED, HG_AGENT);
+    __hip_atomic_store(&st->best, best, __ATOMIC_RELAXED, HG_AGENT);
+    const bool done_now = f >= s && finished == 0u;
+    if (done_now) __hip_atomic_store(&st->finished, 1u, __ATOMIC_RELAXED, HG_AGENT);
+    __hip_atomic_store(&st->lock, 0u, __ATOMIC_SEQ_CST, HG_AGENT);
+    if (done_now) {
+      key_out = best;
+      neval_out = static_cast<int32_t>(min(s * static_cast<uint32_t>(HB),
+                                           static_cast<uint32_t>(a.n_hyp)));
+      return true;
+    }
+    // a round may have completed while the lock was held: merge it too
+    if (!(f < s && __hip_atomic_load(&rdone[f], __ATOMIC_SEQ_CST, HG_AGENT) != 0u)) return false;
+  }
+}
+
 // Shared memory of one workgroup.
 template <int HB>
 struct Smem {
@@ -145,6 +230,8 @@ struct Smem {
   float bestH[9];
   int64_t item;
   uint32_t last;
+  uint32_t skip;
+  int32_t neval;
   unsigned long long key;
 };
 
@@ -152,8 +239,8 @@ struct Smem {
 template <int HB>
 __device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n, Smem<HB> &sm) {
   if (threadIdx.x == 0) {
-    const unsigned long long key = atomicMax(&a.keys[p], 0ull);   // coherent read
-    sm.key = key;
+    const unsigned long long key = sm.key;
+    if (a.n_eval) a.n_eval[p] = sm.neval;
     if (key != 0ull) {
       const uint32_t hyp = 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
       // the winner is recomputed (same device function, same bits) rather than read
@@ -184,12 +271,25 @@ __device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n
 // Process one work item: pair rank r, hypothesis block hb.
 template <int P, int HB>
 __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
-  const int r = static_cast<int>(item / a.n_hb);
-  const int hb = static_cast<int>(item % a.n_hb);
+  // pair-major items (all blocks of the largest pair first), or round-major
+  // under adaptive termination (round r of every pair before round r + 1)
+  const bool adaptive = a.pst != nullptr;
+  const int r = static_cast<int>(adaptive ? item % a.n_pairs : item / a.n_hb);
+  const int hb = static_cast<int>(adaptive ? item / a.n_pairs : item % a.n_hb);
   const int p = a.order ? a.order[r] : r;
   int64_t base;
   uint32_t n;
   pair_range(a, p, base, n);
+  if (adaptive) {
+    // rounds at or past a known stopping point are not evaluated
+    if (threadIdx.x == 0)
+      sm.skip = static_cast<uint32_t>(hb) >=
+                __hip_atomic_load(&a.pst[p].stop, __ATOMIC_RELAXED, HG_AGENT);
+    __syncthreads();
+    const bool skip = sm.skip != 0u;
+    __syncthreads();
+    if (skip) return;
+  }
   const int h0 = hb * HB;
   const int nh = min(HB, a.n_hyp - h0);
   // 1. solve this block's hypotheses, one per thread
@@ -229,22 +329,33 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
     if (t == 0) {
       if (a.blockbest) {
         a.blockbest[item] = key;     // reduced by the mask kernel
+      } else if (adaptive) {
+        const int64_t slot = static_cast<int64_t>(p) * a.n_hb + hb;
+        __hip_atomic_store(&a.rkey[slot], key, __ATOMIC_RELAXED, HG_AGENT);
+        __hip_atomic_store(&a.rdone[slot], 1u, __ATOMIC_SEQ_CST, HG_AGENT);
+        unsigned long long fk = 0ull;
+        int32_t ne = 0;
+        sm.last = adaptive_advance(a, p, n, HB, fk, ne) ? 1u : 0u;
+        sm.key = fk;
+        sm.neval = ne;
       } else {
         if (key != 0ull) atomicMax(&a.keys[p], key);
         // release this block's results, then count it; the last block of the pair
         // (all blocks' keys are in) writes the pair's mask
         __threadfence();
-        sm.last = (atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1));
+        const bool last = atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1);
+        sm.last = last ? 1u : 0u;
+        if (last) {
+          __threadfence();
+          sm.key = atomicMax(&a.keys[p], 0ull);   // coherent read of the final key
+          sm.neval = a.n_hyp;
+        }
       }
     }
   }
   if (a.blockbest) return;
   __syncthreads();
-  if (sm.last) {
-    if (threadIdx.x == 0) __threadfence();
-    __syncthreads();
-    finish_pair<HB>(a, p, base, n, sm);
-  }
+  if (sm.last) finish_pair<HB>(a, p, base, n, sm);
   __syncthreads();
 }
 
@@ -304,8 +415,20 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0 && a.queue) *a.queue = 0u;
   if (p < a.n_pairs) {
-    a.keys[p] = 0ull;
-    a.done[p] = 0u;
+    if (a.keys) a.keys[p] = 0ull;
+    if (a.done) a.done[p] = 0u;
+    if (a.pst) {
+      a.pst[p].best = 0ull;
+      a.pst[p].front = 0u;
+      a.pst[p].stop = static_cast<uint32_t>(a.n_hb);
+      a.pst[p].lock = 0u;
+      a.pst[p].finished = 0u;
+    }
+  }
+  if (a.rdone) {
+    const int64_t total = static_cast<int64_t>(a.n_pairs) * a.n_hb;
+    for (int64_t i = p; i < total; i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      a.rdone[i] = 0u;
   }
   if (!a.order) return;
   int32_t *order = const_cast<int32_t *>(a.order);
@@ -574,6 +697,11 @@ static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, i
   a.order = nullptr;
   a.hbuf = nullptr;
   a.blockbest = nullptr;
+  a.pst = nullptr;
+  a.rkey = nullptr;
+  a.rdone = nullptr;
+  a.n_eval = nullptr;
+  a.one_minus_conf = 0.0;
   return a;
 }
 
@@ -781,6 +909,52 @@ done:
     write_tune_file();
   }
   return HG_OK;
+}
+
+// ---- adaptive termination ---------------------------------------------------
+
+constexpr int kRound = 64;   // hypotheses per round (one work item)
+
+static size_t adaptive_extra_bytes(int n_pairs, int n_hyp) {
+  const int64_t nr = (static_cast<int64_t>(n_hyp) + kRound - 1) / kRound;
+  return align256(sizeof(PairState) * static_cast<size_t>(n_pairs)) +
+         align256(8ull * n_pairs * nr) + align256(4ull * n_pairs * nr);
+}
+
+extern "C" size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max) {
+  if (n_pairs < 1) n_pairs = 1;
+  if (n_hyp_max < 1) n_hyp_max = 1;
+  return batched_ws_bytes(n_pairs) + adaptive_extra_bytes(n_pairs, n_hyp_max);
+}
+
+extern "C" int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off,
+                                  int32_t n_pairs, int32_t n_hyp_max, float thresh, uint64_t seed,
+                                  double confidence, const hg_ransac_tuning *tune, float *best_H,
+                                  int32_t *best_count, int32_t *best_hyp, uint8_t *inlier_mask,
+                                  int32_t *n_evaluated, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  HG_REQUIRE(n_evaluated, "hg_ransac_adaptive: NULL n_evaluated");
+  HG_REQUIRE(confidence > 0.0 && confidence < 1.0, "hg_ransac_adaptive: confidence must be in (0, 1)");
+  if (int st = check_batched(corr, ld, off, n_pairs, n_hyp_max, thresh, tune, best_H, best_count,
+                             best_hyp, inlier_mask, ws, ws_bytes))
+    return st;
+  const size_t need = hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max);
+  if (ws_bytes < need)
+    return fail(HG_EWORKSPACE, "hg_ransac_adaptive: workspace of %zu bytes needed, %zu given",
+                need, ws_bytes);
+  hg_ransac_tuning t = tune ? *tune : lookup_tune(n_pairs, n_hyp_max);
+  t.hyps_per_block = kRound;   // a work item is one round
+  RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp_max, kRound, thresh, seed, best_H,
+                           best_count, best_hyp, inlier_mask, nullptr);
+  char *x = static_cast<char *>(ws) + batched_ws_bytes(n_pairs);
+  a.pst = reinterpret_cast<PairState *>(x);
+  x += align256(sizeof(PairState) * static_cast<size_t>(n_pairs));
+  a.rkey = reinterpret_cast<unsigned long long *>(x);
+  x += align256(8ull * n_pairs * a.n_hb);
+  a.rdone = reinterpret_cast<uint32_t *>(x);
+  a.n_eval = n_evaluated;
+  a.one_minus_conf = 1.0 - confidence;
+  return launch_batched(a, t, ws, as_stream(stream));
 }
 
 struct hg_graph {

@@ -136,3 +136,22 @@ def test_stream_copy_validation(lib):
     assert lib.hg_stream_copy(FAKE, FAKE, -1, None) == _abi.HG_EINVAL
     assert lib.hg_stream_copy(None, FAKE, 5, None) == _abi.HG_EINVAL
     assert lib.hg_stream_copy(None, None, 0, None) == _abi.HG_OK
+
+
+def test_adaptive_validation(lib):
+    need = lib.hg_ransac_adaptive_ws_bytes(512, 1000)
+    assert need > lib.hg_ransac_batched_ws_bytes(512, 1000)
+    ws = C.c_void_p(0x100000)
+
+    def call(**kw):
+        a = dict(conf=0.99, ne=FAKE, n_pairs=512, wsb=need, th=3.0)
+        a.update(kw)
+        return lib.hg_ransac_adaptive(FAKE, 10, FAKE, a["n_pairs"], 1000, a["th"], 1, a["conf"], None,
+                                      FAKE, FAKE, FAKE, FAKE, a["ne"], ws, a["wsb"], None)
+
+    assert call(conf=1.0) == _abi.HG_EINVAL
+    assert call(conf=0.0) == _abi.HG_EINVAL
+    assert call(ne=None) == _abi.HG_EINVAL
+    assert call(n_pairs=0) == _abi.HG_EINVAL
+    assert call(th=0.0) == _abi.HG_EINVAL
+    assert call(wsb=need - 1) == _abi.HG_EWORKSPACE

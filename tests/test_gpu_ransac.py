@@ -227,3 +227,87 @@ def test_config3_persistent_graph_and_autotune():
     for k in replay:
         assert np.array_equal(replay[k], again[k]), k
     g.close()
+
+
+# ---- adaptive termination ------------------------------------------------------
+
+def check_adaptive_pair(corr, n_hyp_max, seed, pair, got, label):
+    ref = oref.ransac_adaptive_ref(corr, n_hyp_max, TAU, seed, pair=pair)
+    m_gpu = int(got["n_eval"])
+    m_ref = ref["n_eval"]
+    valid, lo, hi = ref["valid"], ref["count_lo"], ref["count_hi"]
+    exact = bool((lo[valid] == hi[valid]).all())
+    if exact:
+        assert m_gpu == m_ref, (label, m_gpu, m_ref)
+    assert m_gpu % 64 == 0 or m_gpu == n_hyp_max, label
+    bh, bc = int(got["best_hyp"]), int(got["best_count"])
+    v = valid[:m_gpu]
+    if not v.any():
+        assert bh == -1 and bc == 0 and not got["mask"].any()
+        return ref
+    assert 0 <= bh < m_gpu and valid[bh], label
+    assert lo[bh] <= bc <= hi[bh], label
+    assert bc >= lo[:m_gpu][v].max(), label
+    if exact and m_gpu == m_ref:
+        assert bh == ref["best_hyp"] and bc == ref["best_count"], label
+    Hg = got["best_H"].reshape(3, 3)
+    assert hg.herr(Hg, ref["H32"][bh].astype(np.float64)) <= 1e-5, label
+    d = oref.transfer_error(ref["H32"][bh:bh + 1], corr)[0]
+    band = np.maximum(oref.decision_band(ref["H32"][bh:bh + 1], corr, TAU)[0], 1e-4)
+    ex = np.abs(d - TAU) <= band
+    mk = got["mask"].astype(bool)
+    assert np.array_equal(mk[~ex], (d <= TAU)[~ex]), label
+    assert int(mk.sum()) == bc
+    return ref
+
+
+def test_adaptive_termination_against_oracle():
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    cb = synth.correspondence_batch(40, 41, n_min=60, n_max=3000)
+    corr = torch.from_numpy(cb.corr).cuda()
+    off = torch.from_numpy(cb.off).cuda()
+    ar = hgpu.AdaptiveRansac(corr, off, 1000, TAU, 17, confidence=0.99)
+    ref = None
+    for tune in ((8, 64, 1), (8, 64, 4), (16, 64, 2), (16, 64, 8), None):
+        announce(f"adaptive 40 pairs tuning {tune}")
+        ar.run(tune)
+        torch.cuda.synchronize()
+        out = dict(best_H=ar.best_H.cpu().numpy(), best_count=ar.best_count.cpu().numpy(),
+                   best_hyp=ar.best_hyp.cpu().numpy(), n_eval=ar.n_evaluated.cpu().numpy(),
+                   mask=ar.mask.cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            for k in ref:
+                assert np.array_equal(ref[k], out[k]), (k, tune)
+    evals = []
+    for p in range(40):
+        a, b = cb.off[p], cb.off[p + 1]
+        got = dict(best_H=ref["best_H"][p], best_count=ref["best_count"][p],
+                   best_hyp=ref["best_hyp"][p], n_eval=ref["n_eval"][p], mask=ref["mask"][a:b])
+        check_adaptive_pair(cb.corr[:, a:b], 1000, 17, p, got, f"adaptive pair {p}")
+        evals.append(int(ref["n_eval"][p]))
+    print("adaptive n_evaluated", evals)
+    assert min(evals) < 1000 and max(evals) <= 1000
+
+
+def test_adaptive_extremes():
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    sets = [synth.correspondences(500, 0.95, 51), synth.correspondences(500, 0.05, 52),
+            synth.correspondences(4, 1.0, 53)]
+    corr = np.concatenate([s.corr for s in sets], axis=1)
+    off = np.array([0, 500, 1000, 1004], np.int64)
+    ar = hgpu.AdaptiveRansac(torch.from_numpy(corr).cuda(), torch.from_numpy(off).cuda(), 700, TAU, 3)
+    announce("adaptive extremes")
+    ar.run()
+    torch.cuda.synchronize()
+    ne = ar.n_evaluated.cpu().numpy()
+    assert ne[0] == 64            # 95 % inliers: one round is enough
+    assert ne[1] == 700           # 5 % inliers: the cap
+    for p in range(3):
+        a, b = off[p], off[p + 1]
+        got = dict(best_H=ar.best_H[p].cpu().numpy(), best_count=int(ar.best_count[p]),
+                   best_hyp=int(ar.best_hyp[p]), n_eval=int(ne[p]), mask=ar.mask[a:b].cpu().numpy())
+        check_adaptive_pair(corr[:, a:b], 700, 3, p, got, f"extreme {p}")

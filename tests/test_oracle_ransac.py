@@ -131,3 +131,40 @@ def test_config2_planted_model_found():
     recall = (ref["mask"].astype(bool) & cs.inlier).sum() / cs.inlier.sum()
     assert recall > 0.6
     assert ref["count_lo"].sum() <= ref["counts"].sum() <= ref["count_hi"].sum()
+
+
+def test_required_iterations_matches_paper():
+    # the GPU experiment pairs sample numbers with outlier proportions at 99 %
+    # confidence: 10 / 22 %, 100 / 54 %, 1K / 74 %, 10K / 85 %, 100K / 92 %, 1M / 95 %
+    # (approximate values), and a cap of 1000 loops with a minimum inlier ratio of 26 %
+    import math
+    for n_samp, outlier in ((10, 0.22), (100, 0.54), (1000, 0.74), (10_000, 0.85),
+                            (100_000, 0.92), (1_000_000, 0.95)):
+        k = ransac.required_iterations(1.0 - outlier, 0.99)
+        assert abs(math.log10(k) - math.log10(n_samp)) < 0.15, (n_samp, k)   # rounded ratios
+    assert 990 <= ransac.required_iterations(0.26) <= 1010
+    assert ransac.required_iterations(1.0) == 1
+    assert ransac.required_iterations(0.0) == math.inf
+    # monotone in the inlier ratio
+    ks = [ransac.required_iterations(e) for e in np.linspace(0.05, 0.99, 50)]
+    assert all(a >= b for a, b in zip(ks, ks[1:]))
+
+
+def test_adaptive_reference():
+    cs = synth.correspondences(1500, 0.6, 12)
+    full = ransac.ransac_ref(cs.corr, 1024, 3.0, seed=5)
+    ad = ransac.ransac_adaptive_ref(cs.corr, 1024, 3.0, seed=5)
+    m = ad["n_eval"]
+    assert m % 64 == 0 and 64 <= m < 1024           # 60 % inliers stops early
+    # the stopping rule holds at m and fails one round earlier
+    eps = ad["best_count"] / 1500
+    assert m >= ransac.required_iterations(eps)
+    if m > 64:
+        c_prev = np.where(full["valid"][:m - 64], full["counts"][:m - 64], -1).max()
+        assert m - 64 < ransac.required_iterations(c_prev / 1500)
+    # best over the evaluated prefix
+    c = np.where(full["valid"][:m], full["counts"][:m], -1)
+    assert ad["best_hyp"] == int(np.argmax(c))
+    # a low inlier ratio runs to the cap
+    cs2 = synth.correspondences(800, 0.12, 13)
+    assert ransac.ransac_adaptive_ref(cs2.corr, 640, 3.0, seed=1)["n_eval"] == 640

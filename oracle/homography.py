@@ -433,6 +433,80 @@ def sks64(src, dst):
 
 
 # ---------------------------------------------------------------------------
+# Simplified SK (Sec. 3.4, eq. SK): homography up to a similarity between a
+# known object pattern and its images. The object's anchors M, N fix a
+# canonical frame once per pattern (H_S1 is then never formed per problem), so
+# P5, Q5 and Q7 of the pattern are constants and each image only pays for
+# H_S2, P6, Q8, the kernel parameters and H_S2^-1 H_K (Table III, second row).
+
+def sk_pattern_s(obj):
+    """Per-pattern constants of the simplified SK for the object points
+    ``obj`` = M N P Q (8 numbers, object coordinates).
+
+    Returns (P5x, P5y, kp, km, HS1): P5 is the pattern's P after H_S1 and the
+    swap H_E, kp = 1 / (Q7.x + Q7.y) and km = 1 / (Q7.x - Q7.y) with
+    Q7 = Q5 - P5 (the denominators of the (a, b) solve), and HS1 is the
+    similarity of eq. 3_2_4 as a matrix, so that the complete homography is
+    H = Hbar H_S1 up to scale."""
+    (M1x, M1y), (N1x, N1y), (P1x, P1y), (Q1x, Q1y) = _pts(obj)
+    O1x, O1y, ON1x, ON1y, f1 = _similarity_s(M1x, M1y, N1x, N1y)
+    P3x, P3y = _canon_s(O1x, O1y, ON1x, ON1y, P1x, P1y)
+    r = 1 / P3y
+    P5x, P5y = P3x * r, f1 * r
+    Q3x, Q3y = _canon_s(O1x, O1y, ON1x, ON1y, Q1x, Q1y)
+    r = 1 / Q3y
+    Q7x, Q7y = Q3x * r - P5x, f1 * r - P5y
+    kp = 1 / (Q7x + Q7y)
+    km = 1 / (Q7x - Q7y)
+    z = _zero(M1x)
+    tx = -(ON1x * O1x + ON1y * O1y)
+    ty = ON1y * O1x - ON1x * O1y
+    HS1 = [[ON1x, ON1y, tx], [-ON1y, ON1x, ty], [z, z, f1]]
+    return P5x, P5y, kp, km, HS1
+
+
+def sk_simplified_s(pattern, dst):
+    """Hbar = H_S2^-1 H_K (eq. SK) for one image ``dst`` = M2 N2 P2 Q2 of the
+    pattern whose constants ``pattern`` come from ``sk_pattern_s``; Hbar maps
+    the pattern's canonical frame to the image. The steps are those of SKS on
+    the target side; the (a, b) solve multiplies by the pattern's reciprocals
+    kp, km instead of dividing."""
+    P5x, P5y, kp, km = pattern[:4]
+    (M2x, M2y), (N2x, N2y), (P2x, P2y), (Q2x, Q2y) = _pts(dst)
+    O2x, O2y, ON2x, ON2y, f2 = _similarity_s(M2x, M2y, N2x, N2y)
+    P4x, P4y = _canon_s(O2x, O2y, ON2x, ON2y, P2x, P2y)
+    r = 1 / P4y
+    P6x, P6y = P4x * r, f2 * r
+    Q4x, Q4y = _canon_s(O2x, O2y, ON2x, ON2y, Q2x, Q2y)
+    r = 1 / Q4y
+    Q8x, Q8y = Q4x * r - P6x, f2 * r - P6y
+    s = (Q8x + Q8y) * kp       # a + b
+    d = (Q8x - Q8y) * km       # a - b
+    h = _half(s)
+    a = (s + d) * h
+    b = (s - d) * h
+    u = P6x - a * P5x - b * P5y
+    v = P6y - b * P5x - a * P5y
+    return [[ON2x * a + O2x * b, ON2x * u - ON2y + O2x * v, ON2x * b + O2x * a],
+            [ON2y * a + O2y * b, ON2y * u + ON2x + O2y * v, ON2y * b + O2y * a],
+            [b, v, a]]
+
+
+def sk64(obj, dst):
+    """Vectorised simplified SK: one pattern ``obj`` (8 floats) and SoA target
+    planes (8, n) in float64. Returns (Hbar (n, 3, 3), H_S1 (3, 3))."""
+    pat = sk_pattern_s([float(v) for v in obj])
+    d = np.asarray(dst, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        H = sk_simplified_s(pat, list(d))
+    out = np.empty((d.shape[1], 3, 3))
+    for i in range(3):
+        for j in range(3):
+            out[:, i, j] = H[i][j]
+    return out, np.array(pat[4], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
 # Rectangle source (Sec. 5.3, eqs. H_A1_square .. H_square; Algorithm 1).
 
 def aca_rect_s(x0, y0, w, r, dst, square=False):
@@ -502,6 +576,29 @@ def affine_aca_s(src3, dst3):
     return H
 
 
+def affine_normalised_s(src3, dst3):
+    """The affine map of ``affine_aca_s`` with its third row brought to
+    (0, 0, 1): the top two rows multiplied by 1 / f_A1 (one division and six
+    multiplications). Returns the 2 x 3 matrix [A | t] with x' = A x + t."""
+    H = affine_aca_s(src3, dst3)
+    r = 1 / H[2][2]
+    return [[H[0][0] * r, H[0][1] * r, H[0][2] * r], [H[1][0] * r, H[1][1] * r, H[1][2] * r]]
+
+
+def affine64(src, dst):
+    """Vectorised normalised affine over SoA planes (6, n) in float64;
+    returns (n, 2, 3) (inf or nan where f_A1 = 0)."""
+    s = np.asarray(src, np.float64)
+    d = np.asarray(dst, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        A = affine_normalised_s(list(s), list(d))
+    out = np.empty((s.shape[1], 2, 3))
+    for i in range(2):
+        for j in range(3):
+            out[:, i, j] = A[i][j]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Degeneracy flag, scaling, comparison (conventions of this implementation;
 # the paper defines H only up to scale and has no degeneracy handling).
@@ -551,6 +648,43 @@ def degeneracy_flags(src, dst, delta=DELTA_PX):
     fin = np.isfinite(s).all(axis=0) & np.isfinite(d).all(axis=0)
     with np.errstate(invalid="ignore"):
         near = min_height(s, d) <= delta
+    return (np.where(near & fin, FLAG_NEAR_DEGENERATE, 0)
+            | np.where(fin, 0, FLAG_NONFINITE_INPUT)).astype(np.uint8)
+
+
+def triangle_heights(t):
+    """Height of the triangle M N P over its longest edge for planes (6, n)
+    ``xM yM xN yN xP yP`` (float64)."""
+    t = np.asarray(t, np.float64)
+    X, Y = t[0::2], t[1::2]
+    A = np.abs((X[1] - X[0]) * (Y[2] - Y[0]) - (Y[1] - Y[0]) * (X[2] - X[0]))
+    L2 = [(X[j] - X[i]) ** 2 + (Y[j] - Y[i]) ** 2 for i, j in ((0, 1), (0, 2), (1, 2))]
+    Lm = np.maximum(np.maximum(L2[0], L2[1]), L2[2])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(Lm > 0, A / np.sqrt(Lm), 0.0)
+
+
+def affine_flags(src, dst, delta=DELTA_PX):
+    """Flag bits of the 3-point affine problem: bit0 iff the triangle M N P of
+    either side has height <= delta, bit1 iff an input is not finite."""
+    s = np.asarray(src, np.float64)
+    d = np.asarray(dst, np.float64)
+    fin = np.isfinite(s).all(axis=0) & np.isfinite(d).all(axis=0)
+    with np.errstate(invalid="ignore"):
+        near = np.minimum(triangle_heights(s), triangle_heights(d)) <= delta
+    return (np.where(near & fin, FLAG_NEAR_DEGENERATE, 0)
+            | np.where(fin, 0, FLAG_NONFINITE_INPUT)).astype(np.uint8)
+
+
+def sk_flags(obj, dst, delta=DELTA_PX):
+    """Flag bits of the simplified SK: bit0 iff a triangle of the pattern
+    ``obj`` (8 numbers) or of the image quadruple has height <= delta, bit1
+    iff an image coordinate is not finite."""
+    d = np.asarray(dst, np.float64)
+    pat_thin = bool(side_heights(np.asarray(obj, np.float64)[:, None]).min() <= delta)
+    fin = np.isfinite(d).all(axis=0)
+    with np.errstate(invalid="ignore"):
+        near = (side_heights(d).min(axis=0) <= delta) | pat_thin
     return (np.where(near & fin, FLAG_NEAR_DEGENERATE, 0)
             | np.where(fin, 0, FLAG_NONFINITE_INPUT)).astype(np.uint8)
 

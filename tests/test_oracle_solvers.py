@@ -192,6 +192,70 @@ def test_sks_invariants(int_quads):
         assert proportional(hg.matmul3(hg.matmul3(HS2inv, HK), HS1), H)
 
 
+def test_sk_simplified_exact(int_quads):
+    """Simplified SK (eq. SK): Hbar H_S1 is the homography through the four
+    correspondences, H_S1 takes the pattern's anchors to (-1, 0), (1, 0), and
+    Hbar takes those canonical anchors to the image's anchors (exact)."""
+    n = 0
+    for s, d in int_quads:
+        try:
+            pat = hg.sk_pattern_s(s)
+            Hb = hg.sk_simplified_s(pat, d)
+        except ZeroDivisionError:
+            continue          # a Q7 denominator of the pattern vanishes
+        HS1 = pat[4]
+        assert proportional(hg.matmul3(Hb, HS1), hg.dlt_s(s, d))
+        for k, x in ((0, -1), (1, 1)):
+            u, v, w = hg.apply3(HS1, s[2 * k], s[2 * k + 1])
+            assert (u / w, v / w) == (x, 0)
+            u, v, w = hg.apply3(Hb, Fraction(x), Fraction(0))
+            assert (u / w, v / w) == (d[2 * k], d[2 * k + 1])
+        n += 1
+    assert n >= 190
+    # a pattern already in its canonical frame: H_S1 is a multiple of I and
+    # Hbar is the homography itself
+    obj = [Fraction(v) for v in (-1, 0, 1, 0, 3, 7, -2, 5)]
+    d = [Fraction(v) for v in (10, 12, 61, 8, 14, 47, 55, 52)]
+    pat = hg.sk_pattern_s(obj)
+    assert proportional(pat[4], [[1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    assert proportional(hg.sk_simplified_s(pat, d), hg.dlt_s(obj, d))
+
+
+def test_affine_normalised_exact():
+    """Three correspondences of a known integer affine map give back exactly
+    that map (the 2 x 3 [A | t] with x' = A x + t)."""
+    rng = np.random.default_rng(12)
+    n = 0
+    for _ in range(100):
+        A = [[Fraction(int(v)) for v in rng.integers(-5, 6, 3)] for _ in range(2)]
+        src = [Fraction(int(v)) for v in rng.integers(-20, 20, 6)]
+        (x0, y0), (x1, y1), (x2, y2) = src[0:2], src[2:4], src[4:6]
+        if (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0) == 0:
+            continue
+        dst = []
+        for k in range(3):
+            x, y = src[2 * k], src[2 * k + 1]
+            dst += [A[0][0] * x + A[0][1] * y + A[0][2], A[1][0] * x + A[1][1] * y + A[1][2]]
+        assert hg.affine_normalised_s(src, dst) == A
+        n += 1
+    assert n >= 90
+
+
+def test_affine_and_sk_flags():
+    # exactly collinear triangle on either side, a NaN; flags of a generic set clear
+    src, dst, _ = synth.quadruples(4, 3)
+    src[:, 0] = [0, 0, 10, 10, 20, 20, 5, 40]
+    dst[:6, 1] = [1, 1, 2, 2, 3, 3]
+    src[3, 2] = np.nan
+    f = hg.affine_flags(src[:6], dst[:6])
+    assert list(f) == [1, 1, 2, 0]
+    obj = [0.0, 0.0, 100.0, 0.0, 0.0, 80.0, 120.0, 90.0]
+    g = hg.sk_flags(obj, dst)
+    assert g[1] == 1 and g[0] == 0 and g[3] == 0
+    # a pattern with three collinear points flags every image
+    assert (hg.sk_flags([0, 0, 100, 0, 50, 0, 120, 90], dst[:, 2:]) == 1).all()
+
+
 def test_rect_algorithm1(int_quads):
     rng = np.random.default_rng(9)
     for _ in range(100):
@@ -264,6 +328,14 @@ def test_flop_counts():
     # the Q7 and Q8 steps, all other steps match the table
     _, c = flops.count(hg.sks_s, s, d)
     assert c.flops == 161 and c.div == 6
+    # simplified SK per image (the pattern constants are paid once): Table III
+    # gives 73; the same two extra operations in the Q8 step give 75
+    pat = hg.sk_pattern_s(s)
+    _, c = flops.count(lambda b: hg.sk_simplified_s(pat, b), d)
+    assert c.flops == 75 and c.div == 2
+    # normalised affine: 33 plus one division and six multiplications
+    _, c = flops.count(hg.affine_normalised_s, s[:6], d[:6])
+    assert c.flops == 43 and c.div == 1
 
 
 def test_aca64_fp64_error_against_exact():

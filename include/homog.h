@@ -73,6 +73,46 @@ enum { HG_FLAG_NEAR_DEGENERATE = 1, HG_FLAG_NONFINITE_INPUT = 2, HG_FLAG_ZERO_H 
 int hg_solve4(int method, const float *src, const float *dst, int64_t n, int64_t ld,
               float *H, uint8_t *flags, void *stream);
 
+/* ---- simplified SK: one known pattern, many images ----------------------
+ * The homography up to a similarity of Sec. 3.4 (eq. SK), for the case of a
+ * known planar pattern seen in n images: Hbar = H_S2^-1 H_K = H H_S1^-1, where
+ * H_S1 is the similarity of eq. 3_2_4 that takes the pattern's anchors M, N to
+ * (-1, 0) and (1, 0). The pattern's constants are computed once per call on
+ * the host, so each image costs the per-image steps of Table III (second row).
+ *   obj     HOST array of 8 doubles: the pattern's x_M y_M x_N y_N x_P y_P
+ *           x_Q y_Q in object coordinates (read during the call only).
+ *   dst     8 planes of n floats at stride ld: the images of M, N, P, Q.
+ *   H       9 planes of n floats at stride ld (output): Hbar, which maps the
+ *           pattern's canonical frame to the image, scaled as in hg_solve4.
+ *           The object-to-image homography is Hbar * H_S1 up to scale.
+ *   flags   n bytes (output, may be NULL), bits as in hg_solve4; bit0 is set
+ *           on every problem when a triangle of the pattern itself has height
+ *           <= 1e-2 (in object units).
+ *   frame   HOST array of 9 doubles (output, may be NULL): H_S1 row-major.
+ * A pattern with three collinear points makes every Hbar non-finite: those
+ * are written as zeros with bit2. n == 0 is a no-op (frame is still written).
+ * Errors: NULL obj, a non-finite pattern coordinate, NULL dst or H when
+ * n > 0, n < 0, ld < n -> HG_EINVAL.                                        */
+int hg_solve_sk(const double *obj, const float *dst, int64_t n, int64_t ld, float *H,
+                uint8_t *flags, double *frame, void *stream);
+
+/* ---- three-point affine ---------------------------------------------------
+ * The affine map through three correspondences M, N, P as H_A2^-1 H_A1
+ * (Sec. 4.4, eq. AffineACA, 33 operations up to scale), normalised by its
+ * third-row entry f_A1 (one division, six multiplications), in double
+ * precision on float inputs.
+ *   src, dst  6 planes each of n floats at stride ld: x_M y_M x_N y_N x_P y_P.
+ *   A         6 planes of n floats at stride ld (output): a11 a12 a13 a21 a22
+ *             a23 with (x', y') = A (x, y, 1).
+ *   flags     n bytes (output, may be NULL): bit0 = the triangle M N P of
+ *             either side has height <= 1e-2 px; bit1 = non-finite input;
+ *             bit2 = A was not finite (source triangle of zero area) and has
+ *             been written as zeros.
+ * n == 0 is a no-op. Errors: NULL pointer (other than flags), n < 0, ld < n
+ * -> HG_EINVAL.                                                              */
+int hg_solve3_affine(const float *src, const float *dst, int64_t n, int64_t ld, float *A,
+                     uint8_t *flags, void *stream);
+
 /* Plain device copy of n floats with the access pattern of hg_solve4 (one
  * float per lane, 512-thread workgroups, non-temporal loads and stores). Not
  * part of the method: it is the reference for calibrating hardware byte

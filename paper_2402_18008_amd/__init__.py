@@ -64,6 +64,48 @@ def hg_solve4(src, dst, method=HG_ACA, H=None, flags=None, stream=None):
 solve4 = hg_solve4
 
 
+def hg_solve_sk(obj, dst, H=None, flags=None, stream=None):
+    """Simplified SK for one known pattern ``obj`` (8 numbers xM yM xN yN xP yP
+    xQ yQ in object coordinates) and its images ``dst`` ((8, n) float32
+    planes). Returns (Hbar (9, n) planes, flags (n,), H_S1 (3, 3) float64
+    numpy array) with the object-to-image homography Hbar H_S1 up to scale."""
+    import numpy as np
+    o = (C.c_double * 8)(*[float(v) for v in obj])
+    frame = (C.c_double * 9)()
+    ld = _planes(dst, "dst", 8)
+    n = dst.shape[1]
+    if H is None:
+        H = torch.empty((9, ld), dtype=torch.float32, device=dst.device)[:, :n]
+    elif _planes(H, "H", 9) != ld:
+        raise ValueError("H must share the plane stride of dst")
+    if flags is None:
+        flags = torch.empty(n, dtype=torch.uint8, device=dst.device)
+    _dev(flags, "flags", torch.uint8)
+    _abi.call("hg_solve_sk", o, dst.data_ptr(), n, ld, H.data_ptr(), flags.data_ptr(), frame,
+              _stream(stream))
+    return H, flags, np.array(list(frame), dtype=np.float64).reshape(3, 3)
+
+
+def hg_solve3_affine(src, dst, A=None, flags=None, stream=None):
+    """Affine map through three correspondences for every column of
+    ``src``/``dst`` ((6, n) float32 planes xM yM xN yN xP yP sharing one plane
+    stride). Returns (A (6, n) planes a11 a12 a13 a21 a22 a23, flags (n,))."""
+    ld = _planes(src, "src", 6)
+    if _planes(dst, "dst", 6) != ld:
+        raise ValueError("src and dst must share the plane stride")
+    n = src.shape[1]
+    if A is None:
+        A = torch.empty((6, ld), dtype=torch.float32, device=src.device)[:, :n]
+    elif _planes(A, "A", 6) != ld:
+        raise ValueError("A must share the plane stride of src")
+    if flags is None:
+        flags = torch.empty(n, dtype=torch.uint8, device=src.device)
+    _dev(flags, "flags", torch.uint8)
+    _abi.call("hg_solve3_affine", src.data_ptr(), dst.data_ptr(), n, ld, A.data_ptr(),
+              flags.data_ptr(), _stream(stream))
+    return A, flags
+
+
 def hg_stream_copy(src, dst=None, stream=None):
     """Copy a float32 tensor with the solver's access pattern (reference for
     byte counters and streaming ceilings)."""

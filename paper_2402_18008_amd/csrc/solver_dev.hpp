@@ -20,7 +20,7 @@ constexpr double kDelta = 1e-2;           // minimum admissible triangle height,
 constexpr double kDelta2 = kDelta * kDelta;
 
 // Squared edge length between points i and j of one side.
-__device__ __forceinline__ double edge2(const double *x, const double *y, int i, int j) {
+__host__ __device__ __forceinline__ double edge2(const double *x, const double *y, int i, int j) {
   const double dx = x[j] - x[i];
   const double dy = y[j] - y[i];
   return dx * dx + dy * dy;
@@ -30,7 +30,7 @@ __device__ __forceinline__ double edge2(const double *x, const double *y, int i,
 // longest edge: A^2 <= delta^2 * max(edge^2), with A the doubled signed area.
 // The areas of MNP, MQP, MNQ and NPQ are exactly the ACA quantities f_A, Q.x,
 // Q.y and t of that side (eqs. f_A_1, Q3, t1).
-__device__ __forceinline__ bool side_thin(const double *x, const double *y, double aMNP,
+__host__ __device__ __forceinline__ bool side_thin(const double *x, const double *y, double aMNP,
                                           double aMQP, double aMNQ, double aNPQ) {
   const double mn = edge2(x, y, 0, 1), mp = edge2(x, y, 0, 2), mq = edge2(x, y, 0, 3);
   const double np = edge2(x, y, 1, 2), nq = edge2(x, y, 1, 3), pq = edge2(x, y, 2, 3);
@@ -91,7 +91,7 @@ __device__ __forceinline__ uint32_t aca_solve(const double *s, const double *d, 
 }
 
 // Doubled signed areas (MNP, MQP, MNQ, NPQ) of one side, as in ACA.
-__device__ __forceinline__ bool quad_side_thin(const double *q) {
+__host__ __device__ __forceinline__ bool quad_side_thin(const double *q) {
   const double MNx = q[2] - q[0], MNy = q[3] - q[1];
   const double MPx = q[4] - q[0], MPy = q[5] - q[1];
   const double MQx = q[6] - q[0], MQy = q[7] - q[1];
@@ -156,6 +156,83 @@ __device__ __forceinline__ uint32_t sks_solve(const double *s, const double *d, 
   return (quad_side_thin(s) || quad_side_thin(d)) ? kNearDegenerate : 0u;
 }
 
+// Simplified SK (Sec. 3.4, eq. SK): the homography up to a similarity from a
+// known pattern to one image, Hbar = H_S2^-1 H_K, which maps the pattern's
+// canonical frame (anchors at (-1, 0), (1, 0)) to the image. That frame is
+// fixed once per pattern, so the pattern's P5 and the reciprocals
+// kp = 1 / (Q7.x + Q7.y), km = 1 / (Q7.x - Q7.y) are constants; per image
+// only the target-side steps of SKS remain (Table III, second row).
+struct SkPattern {
+  double P5x, P5y, kp, km;
+  uint32_t flags;  // kNearDegenerate if a triangle of the pattern is thin
+};
+
+__device__ __forceinline__ uint32_t sk_simplified_solve(const SkPattern &p, const double *d,
+                                                        double *H) {
+  const double ON2x = (d[2] - d[0]) * 0.5, ON2y = (d[3] - d[1]) * 0.5;
+  const double O2x = d[0] + ON2x, O2y = d[1] + ON2y;
+  const double f2 = ON2x * ON2x + ON2y * ON2y;
+  double dx = d[4] - O2x, dy = d[5] - O2y;
+  const double P4x = ON2x * dx + ON2y * dy, P4y = ON2x * dy - ON2y * dx;
+  double r = 1.0 / P4y;
+  const double P6x = P4x * r, P6y = f2 * r;
+  dx = d[6] - O2x;
+  dy = d[7] - O2y;
+  const double Q4x = ON2x * dx + ON2y * dy, Q4y = ON2x * dy - ON2y * dx;
+  r = 1.0 / Q4y;
+  const double Q8x = Q4x * r - P6x, Q8y = f2 * r - P6y;
+  const double sp = (Q8x + Q8y) * p.kp;  // a + b
+  const double sm = (Q8x - Q8y) * p.km;  // a - b
+  const double a = (sp + sm) * 0.5, b = (sp - sm) * 0.5;
+  const double u = P6x - a * p.P5x - b * p.P5y;
+  const double v = P6y - b * p.P5x - a * p.P5y;
+  // H_S2^-1 H_K with H_K = [[a, u, b], [0, 1, 0], [b, v, a]]
+  H[0] = ON2x * a + O2x * b;
+  H[1] = ON2x * u - ON2y + O2x * v;
+  H[2] = ON2x * b + O2x * a;
+  H[3] = ON2y * a + O2y * b;
+  H[4] = ON2y * u + ON2x + O2y * v;
+  H[5] = ON2y * b + O2y * a;
+  H[6] = b;
+  H[7] = v;
+  H[8] = a;
+  return (p.flags | (quad_side_thin(d) ? kNearDegenerate : 0u));
+}
+
+// Affine map through three correspondences M, N, P (Sec. 4.4, eq. AffineACA):
+// H_A2^-1 H_A1 (33 operations, third row (0, 0, f_A1)), then its top two rows
+// times 1 / f_A1, giving A = [a11 a12 a13; a21 a22 a23] with x' = A (x, y, 1).
+// s, d: x_M y_M x_N y_N x_P y_P. Returns the near-degeneracy bit (the triangle
+// M N P of either side has height <= kDelta).
+__device__ __forceinline__ uint32_t affine_solve(const double *s, const double *d, double *A) {
+  const double M1x = s[0], M1y = s[1];
+  const double MN1x = s[2] - M1x, MN1y = s[3] - M1y;
+  const double MP1x = s[4] - M1x, MP1y = s[5] - M1y;
+  const double fA1 = MN1x * MP1y - MN1y * MP1x;
+  const double MN2x = d[2] - d[0], MN2y = d[3] - d[1];
+  const double MP2x = d[4] - d[0], MP2y = d[5] - d[1];
+  const double rows[2][3] = {{MN2x, MP2x, d[0]}, {MN2y, MP2y, d[1]}};
+  const double r = 1.0 / fA1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double h0 = rows[i][0] * MP1y - rows[i][1] * MN1y;
+    const double h1 = rows[i][1] * MN1x - rows[i][0] * MP1x;
+    const double h2 = rows[i][2] * fA1 - (h0 * M1x + h1 * M1y);
+    A[3 * i + 0] = h0 * r;
+    A[3 * i + 1] = h1 * r;
+    A[3 * i + 2] = h2 * r;
+  }
+  // triangle heights: A^2 <= delta^2 max(edge^2) on each side
+  const double fA2 = MN2x * MP2y - MN2y * MP2x;
+  auto thin = [](const double *q, double area) {
+    const double e0 = (q[2] - q[0]) * (q[2] - q[0]) + (q[3] - q[1]) * (q[3] - q[1]);
+    const double e1 = (q[4] - q[0]) * (q[4] - q[0]) + (q[5] - q[1]) * (q[5] - q[1]);
+    const double e2 = (q[4] - q[2]) * (q[4] - q[2]) + (q[5] - q[3]) * (q[5] - q[3]);
+    return area * area <= kDelta2 * fmax(fmax(e0, e1), e2);
+  };
+  return (thin(s, fA1) || thin(d, fA2)) ? kNearDegenerate : 0u;
+}
+
 // Scale H by the power of two that brings max|h| into [0.5, 1) (exact) and
 // round to float. Zero or non-finite H is written as zeros; returns kZeroH then.
 __device__ __forceinline__ uint32_t scale_to_float(const double *H, float *out) {
@@ -181,6 +258,49 @@ __device__ __forceinline__ uint32_t scale_to_float(const double *H, float *out) 
 
 __device__ __forceinline__ bool finite_f(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
+}
+
+// Simplified SK from the float image quadruple to the scaled float Hbar.
+__device__ __forceinline__ uint32_t solve_sk(const SkPattern &p, const float *d, float *h) {
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) fin = fin && finite_f(d[k]);
+  if (!fin) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = 0.0f;
+    return kNonfiniteInput | kZeroH;
+  }
+  double dd[8], H[9];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) dd[k] = static_cast<double>(d[k]);
+  const uint32_t thin = sk_simplified_solve(p, dd, H);
+  return thin | scale_to_float(H, h);
+}
+
+// Three-point affine from float inputs to the float 2 x 3 map. A non-finite
+// result (f_A1 == 0) is written as zeros with kZeroH.
+__device__ __forceinline__ uint32_t solve_affine(const float *s, const float *d, float *a) {
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) fin = fin && finite_f(s[k]) && finite_f(d[k]);
+  if (!fin) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a[i] = 0.0f;
+    return kNonfiniteInput | kZeroH;
+  }
+  double sd[6], dd[6], A[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    sd[k] = static_cast<double>(s[k]);
+    dd[k] = static_cast<double>(d[k]);
+  }
+  const uint32_t thin = affine_solve(sd, dd, A);
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) bad |= !(fabs(A[i]) <= 1.7976931348623157e308);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a[i] = bad ? 0.0f : static_cast<float>(A[i]);
+  return thin | (bad ? kZeroH : 0u);
 }
 
 // One 4-point problem from float inputs to the scaled float H and its flags.

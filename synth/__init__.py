@@ -189,6 +189,73 @@ def quadruples_parallel(n, seed, degenerate_every=0, workers=8, out=None):
     return src, dst, lab
 
 
+# A planar target in object units (say mm): points M, N, P, Q of a calibration
+# board, as in the known-pattern setting of the simplified SK.
+PATTERN = np.array([20.0, 30.0, 180.0, 25.0, 35.0, 140.0, 170.0, 150.0])
+
+
+def _pattern_chunk(seed, chunk, m, obj):
+    rng = np.random.default_rng([seed, chunk, 0x5C])
+    ox, oy = obj[0::2], obj[1::2]
+    cx, cy = ox.mean(), oy.mean()
+    x = np.broadcast_to(ox - cx, (m, 4))
+    y = np.broadcast_to(oy - cy, (m, 4))
+    H = _random_similarity_persp(rng, m)
+    for _ in range(1000):
+        _, _, w = _apply(H, x, y)
+        bad = np.nonzero(w.min(axis=1) < W_MIN)[0]
+        if bad.size == 0:
+            break
+        H[bad, 2, 0:2] = rng.uniform(-1e-3, 1e-3, (bad.size, 2))
+    else:  # pragma: no cover - probability ~0
+        raise RuntimeError("perspective rejection did not converge")
+    u, v, w = _apply(H, x, y)
+    noise = rng.normal(0.0, 0.5, (m, 4, 2))
+    dst = np.empty((8, m), np.float32)
+    dst[0::2] = (u / w + FRAME_W / 2 + noise[:, :, 0]).T
+    dst[1::2] = (v / w + FRAME_H / 2 + noise[:, :, 1]).T
+    return dst
+
+
+def _pattern_worker(args):
+    seed, c, m, obj = args
+    return c, _pattern_chunk(seed, c, m, obj)
+
+
+def pattern_images(n, seed, obj=PATTERN, workers=1):
+    """Images of one planar pattern ``obj`` (8 numbers M N P Q, object units):
+    per image a random similarity with perspective row (as for quadruples),
+    acting about the pattern's centroid and placed at the frame centre, the
+    perspective redrawn while a point has w < 0.1, plus N(0, 0.5^2) px noise;
+    float32 planes (8, n). Chunks of ``CHUNK`` images are seeded
+    ``(seed, chunk)``; ``workers`` > 1 draws them in a process pool (same
+    result)."""
+    n = int(n)
+    obj = np.asarray(obj, np.float64)
+    dst = np.empty((8, n), np.float32)
+    jobs = [(seed, c, min(CHUNK, n - c * CHUNK), obj) for c in range((n + CHUNK - 1) // CHUNK)]
+    if workers <= 1 or len(jobs) <= 1:
+        results = map(_pattern_worker, jobs)
+        pool = None
+    else:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(max(1, min(workers, len(jobs))))
+        results = pool.imap_unordered(_pattern_worker, jobs)
+    try:
+        for c, d in results:
+            dst[:, c * CHUNK:c * CHUNK + d.shape[1]] = d
+        if pool is not None:
+            pool.close()
+    except BaseException:
+        if pool is not None:
+            pool.terminate()
+        raise
+    finally:
+        if pool is not None:
+            pool.join()
+    return dst
+
+
 @dataclasses.dataclass
 class CorrSet:
     corr: np.ndarray      # (4, n) float32: x1 y1 x2 y2

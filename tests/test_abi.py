@@ -57,6 +57,39 @@ def test_solve4_validation(lib):
     assert f(1, None, None, 0, 0, None, None, None) == _abi.HG_OK
 
 
+def test_sk_and_affine_validation(lib):
+    D8 = C.c_double * 8
+    obj = D8(0.0, 0.0, 100.0, 0.0, 0.0, 80.0, 120.0, 90.0)
+    f = lib.hg_solve_sk
+    assert f(None, FAKE, 10, 10, FAKE, None, None, None) == _abi.HG_EINVAL
+    bad = D8(*obj)
+    bad[5] = float("nan")
+    assert f(bad, FAKE, 10, 10, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert b"pattern" in lib.hg_last_error()
+    assert f(obj, FAKE, -1, 10, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(obj, FAKE, 10, 9, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(obj, None, 10, 10, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(obj, FAKE, 10, 10, None, None, None, None) == _abi.HG_EINVAL
+    g = lib.hg_solve3_affine
+    assert g(FAKE, FAKE, -1, 10, FAKE, None, None) == _abi.HG_EINVAL
+    assert g(FAKE, FAKE, 10, 9, FAKE, None, None) == _abi.HG_EINVAL
+    assert g(None, FAKE, 10, 10, FAKE, None, None) == _abi.HG_EINVAL
+    assert g(FAKE, FAKE, 10, 10, None, None, None) == _abi.HG_EINVAL
+    assert g(None, None, 0, 0, None, None, None) == _abi.HG_OK
+
+
+def test_sk_frame_host_setup(lib):
+    """n == 0 runs only the host-side pattern set-up: the returned frame is the
+    similarity H_S1 of the pattern (host logic; no GPU involved)."""
+    import numpy as np
+    from oracle import homography as hg
+    vals = (3.0, -2.0, 101.5, 7.25, 10.0, 80.0, 120.0, 95.0)
+    frame = (C.c_double * 9)()
+    assert lib.hg_solve_sk((C.c_double * 8)(*vals), None, 0, 0, None, None, frame, None) == 0
+    ref = np.array(hg.sk_pattern_s(list(vals))[4], dtype=np.float64)
+    assert np.array_equal(np.array(list(frame)).reshape(3, 3), ref)
+
+
 def test_ransac_validation(lib):
     f = lib.hg_ransac
     ws_need = lib.hg_ransac_ws_bytes(2000, 4096)

@@ -40,3 +40,17 @@ def test_patches():
     assert np.allclose(pb.img.mean(axis=(1, 2)), 0, atol=1e-5)
     assert np.allclose(pb.img.std(axis=(1, 2)), 1, atol=1e-4)
     assert (np.abs(pb.offsets) <= 32).all()
+
+
+def test_pattern_images():
+    d1 = synth.pattern_images(1000, 4)
+    d2 = synth.pattern_images(1000, 4, workers=2)
+    assert d1.shape == (8, 1000) and d1.dtype == np.float32
+    assert np.array_equal(d1, d2)
+    assert not np.array_equal(d1, synth.pattern_images(1000, 5))
+    # the pattern's centroid lands near the frame centre; sizes follow the scale draw
+    cx = d1[0::2].mean(axis=0)
+    cy = d1[1::2].mean(axis=0)
+    assert abs(np.median(cx) - 320) < 15 and abs(np.median(cy) - 240) < 15
+    span = np.hypot(d1[2] - d1[0], d1[3] - d1[1])          # image of the M N edge (160 units)
+    assert 0.4 * 160 < np.median(span) < 2.5 * 160

@@ -78,6 +78,26 @@ def h_rect(offsets, size):
     return torch.stack([torch.stack(r, dim=-1) for r in H], dim=-2)
 
 
+def h_aca(src, dst):
+    """General ACA (Sec. 4, the structured order of ``homography.aca_s``) on
+    torch tensors: src, dst (B, 8) as x_M y_M x_N y_N x_P y_P x_Q y_Q; returns
+    H (B, 3, 3) at ACA's own scale. Autograd through it gives the reverse mode
+    of the tensorised general solver."""
+    H = hg.aca_s(list(src.T), list(dst.T))
+    return torch.stack([torch.stack(r, dim=-1) for r in H], dim=-2)
+
+
+def aca_vjp(src, dst, grad_H):
+    """(dH/dsrc)^T grad_H and (dH/ddst)^T grad_H, each (B, 8), for H = h_aca
+    and grad_H (B, 3, 3), by float64 autograd."""
+    s = torch.as_tensor(src, dtype=torch.float64).clone().requires_grad_(True)
+    d = torch.as_tensor(dst, dtype=torch.float64).clone().requires_grad_(True)
+    g = torch.as_tensor(grad_H, dtype=torch.float64)
+    H = h_aca(s, d)
+    gs, gd = torch.autograd.grad((H * g).sum(), (s, d))
+    return gs, gd
+
+
 def bilinear_zero(img, sx, sy):
     """Sample img (B, h, w) at (sx, sy) (B, P) with zero padding."""
     B, h, w = img.shape

@@ -98,3 +98,27 @@ def test_loss_zero_at_true_shift():
         a = Iw[b][ys, xs].ravel()
         t = pb.tgt[b][ys, xs].ravel().astype(np.float64)
         assert np.corrcoef(a, t)[0, 1] > 0.999999
+
+
+def test_general_aca_matches_dlt_and_finite_differences():
+    """The tensorised general ACA is the homography through the four
+    correspondences, and its autograd reverse mode agrees with central finite
+    differences of the float64 solver."""
+    src, dst, _ = synth.quadruples(6, 21)
+    s = torch.as_tensor(src.T.astype(np.float64))
+    d = torch.as_tensor(dst.T.astype(np.float64))
+    H = warp.h_aca(s, d).numpy()
+    assert hg.herr(H, hg.dlt64(src.astype(np.float64), dst.astype(np.float64))).max() < 1e-10
+    rng = np.random.default_rng(3)
+    gH = torch.as_tensor(rng.normal(size=(6, 3, 3)))
+    gs, gd = warp.aca_vjp(s, d, gH)
+    for x, g, which in ((s, gs, 0), (d, gd, 1)):
+        fd = torch.zeros_like(g)
+        for k in range(8):
+            e = torch.zeros_like(x)
+            e[:, k] = 1e-4
+            a = (s + e, d) if which == 0 else (s, d + e)
+            b = (s - e, d) if which == 0 else (s, d - e)
+            fd[:, k] = ((warp.h_aca(*a) - warp.h_aca(*b)) * gH).sum((1, 2)) / 2e-4
+        scale = g.abs().max(dim=1, keepdim=True).values
+        assert ((g - fd).abs() <= 1e-7 * scale).all(), (which, (g - fd).abs().max())

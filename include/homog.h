@@ -234,6 +234,20 @@ int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w
 int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32_t B, float x0, float y0,
                     float w, float r, float *grad_offsets, void *stream);
 
+/* General quadrilaterals (the tensorised general ACA of the deep-pipeline
+ * experiments, Sec. 4): src, dst B x 8 floats, rows x_M y_M x_N y_N x_P y_P
+ * x_Q y_Q (point order as hg_solve4).
+ * hg_aca_fwd: H (B x 9 doubles) = H_A2^-1 H_C H_A1 at ACA's own scale (no
+ *   rescaling), double precision inside; no degeneracy test.
+ * hg_aca_bwd: grad_src, grad_dst (B x 8 floats each, either may be NULL) =
+ *   (dH/dsrc)^T grad_H and (dH/ddst)^T grad_H, grad_H B x 9 doubles; the
+ *   forward quantities are recomputed (nothing is stored between the calls).
+ * Errors: B < 0, a NULL input, both outputs NULL -> HG_EINVAL; B == 0 is a
+ * no-op.                                                                    */
+int hg_aca_fwd(const float *src, const float *dst, int32_t B, double *H, void *stream);
+int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t B,
+               float *grad_src, float *grad_dst, void *stream);
+
 /* Photometric loss of the warp by H (B x 9 doubles): for every pixel
  * p = (x, y) of an h x w output (x = column), sample img at pi(adj(H) p)
  * (adj(H) ~ H^-1) bilinearly, x0 = floor(x), taps outside the image reading

@@ -322,6 +322,55 @@ def hg_aca_rect_bwd(offsets, grad_H, x0, y0, w, r, stream=None):
     return g
 
 
+def _quad_rows(t, name):
+    _c(t, name)
+    if t.dim() < 2 or t.shape[-1] * (t.shape[-2] if t.dim() == 3 else 1) != 8:
+        raise ValueError(f"{name} must be (B, 8) or (B, 4, 2)")
+    return t.shape[0]
+
+
+def hg_aca_fwd(src, dst, stream=None):
+    """H (B, 9) float64 at ACA's own scale from general quadrilaterals src,
+    dst ((B, 8) or (B, 4, 2) float32, points M N P Q)."""
+    B = _quad_rows(src, "src")
+    if _quad_rows(dst, "dst") != B:
+        raise ValueError("src and dst must have the same batch size")
+    H = torch.empty((B, 9), dtype=torch.float64, device=src.device)
+    _abi.call("hg_aca_fwd", src.data_ptr(), dst.data_ptr(), B, H.data_ptr(), _stream(stream))
+    return H
+
+
+def hg_aca_bwd(src, dst, grad_H, want_src=True, want_dst=True, stream=None):
+    """(grad_src, grad_dst), each shaped like src (or None when not wanted)."""
+    B = _quad_rows(src, "src")
+    _quad_rows(dst, "dst")
+    _c(grad_H, "grad_H", torch.float64)
+    gs = torch.empty_like(src) if want_src else None
+    gd = torch.empty_like(dst) if want_dst else None
+    _abi.call("hg_aca_bwd", src.data_ptr(), dst.data_ptr(), grad_H.data_ptr(), B,
+              gs.data_ptr() if gs is not None else None,
+              gd.data_ptr() if gd is not None else None, _stream(stream))
+    return gs, gd
+
+
+class ACAGeneral(torch.autograd.Function):
+    """(src, dst) general quadrilaterals -> H (B, 9) float64 by ACA; backward
+    by the hand-written reverse-mode kernel, to both point sets."""
+
+    @staticmethod
+    def forward(ctx, src, dst):
+        src, dst = src.contiguous(), dst.contiguous()
+        ctx.save_for_backward(src, dst)
+        return hg_aca_fwd(src, dst)
+
+    @staticmethod
+    def backward(ctx, grad_H):
+        src, dst = ctx.saved_tensors
+        gs, gd = hg_aca_bwd(src, dst, grad_H.to(torch.float64).contiguous(),
+                            ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return gs, gd
+
+
 def _img3(img, name):
     _c(img, name)
     if img.dim() != 3:

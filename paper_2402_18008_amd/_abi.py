@@ -56,6 +56,8 @@ SIGNATURES = {
     "hg_graph_destroy": (None, [vp]),
     "hg_aca_rect_fwd": (C.c_int, [vp, i32, f32, f32, f32, f32, vp, vp]),
     "hg_aca_rect_bwd": (C.c_int, [vp, vp, i32, f32, f32, f32, f32, vp, vp]),
+    "hg_aca_fwd": (C.c_int, [vp, vp, i32, vp, vp]),
+    "hg_aca_bwd": (C.c_int, [vp, vp, vp, i32, vp, vp, vp]),
     "hg_warp_l1_fwd": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, vp]),
     "hg_warp_l1_bwd": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, vp, vp]),
     "hg_warp_store_fwd": (C.c_int, [vp, vp, i32, i32, i32, vp, vp]),

@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "solver_dev.hpp"
 
 namespace hg {
 
@@ -500,6 +501,47 @@ static int check_img(const void *a, const void *b2, int B, int h, int w, const c
   return HG_OK;
 }
 
+// General quadrilaterals (the tensorised general ACA): src, dst B x 8 floats
+// (x_M y_M x_N y_N x_P y_P x_Q y_Q); H B x 9 doubles at ACA's own scale.
+__global__ void aca_fwd_kernel(const float *__restrict__ src, const float *__restrict__ dst,
+                               int B, double *__restrict__ H) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s[8], d[8], h[9];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    s[k] = static_cast<double>(src[8 * b + k]);
+    d[k] = static_cast<double>(dst[8 * b + k]);
+  }
+  (void)aca_solve(s, d, h);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) H[9 * b + i] = h[i];
+}
+
+__global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__restrict__ dst,
+                               const double *__restrict__ gH, int B, float *__restrict__ gsrc,
+                               float *__restrict__ gdst) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s[8], d[8], g[9], gs[8], gd[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    s[k] = static_cast<double>(src[8 * b + k]);
+    d[k] = static_cast<double>(dst[8 * b + k]);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = gH[9 * b + i];
+  aca_vjp(s, d, g, gs, gd);
+  if (gsrc) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gsrc[8 * b + k] = static_cast<float>(gs[k]);
+  }
+  if (gdst) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gdst[8 * b + k] = static_cast<float>(gd[k]);
+  }
+}
+
 static int check_rect(float w, float r, int B, const char *fn) {
   HG_REQUIRE(B >= 0, "%s: B < 0", fn);
   HG_REQUIRE(std::isfinite(w) && w > 0.0f && std::isfinite(r) && r > 0.0f,
@@ -535,6 +577,29 @@ extern "C" int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32
                      offsets, grad_H, B, static_cast<double>(x0), static_cast<double>(y0),
                      static_cast<double>(w), static_cast<double>(r), grad_offsets);
   return launched("rect_bwd_kernel");
+}
+
+extern "C" int hg_aca_fwd(const float *src, const float *dst, int32_t B, double *H,
+                          void *stream) {
+  clear_error();
+  HG_REQUIRE(B >= 0, "hg_aca_fwd: B < 0");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(src && dst && H, "hg_aca_fwd: NULL pointer");
+  hipLaunchKernelGGL(aca_fwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream), src,
+                     dst, B, H);
+  return launched("aca_fwd_kernel");
+}
+
+extern "C" int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t B,
+                          float *grad_src, float *grad_dst, void *stream) {
+  clear_error();
+  HG_REQUIRE(B >= 0, "hg_aca_bwd: B < 0");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(src && dst && grad_H, "hg_aca_bwd: NULL src, dst or grad_H");
+  HG_REQUIRE(grad_src || grad_dst, "hg_aca_bwd: both gradient outputs are NULL");
+  hipLaunchKernelGGL(aca_bwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream), src,
+                     dst, grad_H, B, grad_src, grad_dst);
+  return launched("aca_bwd_kernel");
 }
 
 extern "C" int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t B,

@@ -45,7 +45,8 @@ __host__ __device__ __forceinline__ bool side_thin(const double *x, const double
 // 7 + 7 FLOPs for the affinities, 28 for the core, 10 + 33 for the product).
 // s, d: x_M y_M x_N y_N x_P y_P x_Q y_Q of source and target. H row-major.
 // Returns the near-degeneracy bit.
-__device__ __forceinline__ uint32_t aca_solve(const double *s, const double *d, double *H) {
+__host__ __device__ __forceinline__ uint32_t aca_solve(const double *s, const double *d,
+                                                          double *H) {
   const double M1x = s[0], M1y = s[1], N1x = s[2], N1y = s[3];
   const double P1x = s[4], P1y = s[5], Q1x = s[6], Q1y = s[7];
   const double M2x = d[0], M2y = d[1], N2x = d[2], N2y = d[3];
@@ -88,6 +89,111 @@ __device__ __forceinline__ uint32_t aca_solve(const double *s, const double *d, 
   const double x2[4] = {M2x, N2x, P2x, Q2x}, y2[4] = {M2y, N2y, P2y, Q2y};
   const bool thin = side_thin(x1, y1, fA1, Q3x, Q3y, t1) || side_thin(x2, y2, fA2, Q4x, Q4y, t2);
   return thin ? kNearDegenerate : 0u;
+}
+
+// Reverse mode of aca_solve: given gH = dL/dH (row-major, H at ACA's own
+// scale), accumulate-free gs = dL/ds and gd = dL/dd (8 each, point order
+// M N P Q). The forward quantities are recomputed, then each step of the
+// forward order is differentiated in reverse: composition H = L H_A1, the
+// product L = H_A2^-1 H_C, the core c11, c22, c33, the signed areas, and the
+// difference vectors.
+__host__ __device__ __forceinline__ void aca_vjp(const double *s, const double *d,
+                                                 const double *gH, double *gs, double *gd) {
+  const double M1x = s[0], M1y = s[1];
+  const double M2x = d[0], M2y = d[1], N2x = d[2], N2y = d[3], P2x = d[4], P2y = d[5];
+  const double MN1x = s[2] - M1x, MN1y = s[3] - M1y;
+  const double MP1x = s[4] - M1x, MP1y = s[5] - M1y;
+  const double MQ1x = s[6] - M1x, MQ1y = s[7] - M1y;
+  const double MN2x = N2x - M2x, MN2y = N2y - M2y;
+  const double MP2x = P2x - M2x, MP2y = P2y - M2y;
+  const double MQ2x = d[6] - M2x, MQ2y = d[7] - M2y;
+  const double fA1 = MN1x * MP1y - MN1y * MP1x;
+  const double fA2 = MN2x * MP2y - MN2y * MP2x;
+  const double Q3x = MQ1x * MP1y - MQ1y * MP1x;
+  const double Q3y = MN1x * MQ1y - MN1y * MQ1x;
+  const double Q4x = MQ2x * MP2y - MQ2y * MP2x;
+  const double Q4y = MN2x * MQ2y - MN2y * MQ2x;
+  const double t1 = fA1 - Q3x - Q3y;
+  const double t2 = fA2 - Q4x - Q4y;
+  const double c11 = t1 * Q3y * Q4x;
+  const double c22 = t1 * Q3x * Q4y;
+  const double c33 = t2 * Q3x * Q3y;
+  const double mx = M2x * c33, my = M2y * c33;
+  const double L[3][3] = {{N2x * c11 - mx, P2x * c22 - mx, mx},
+                          {N2y * c11 - my, P2y * c22 - my, my},
+                          {c11 - c33, c22 - c33, c33}};
+  // H row i: h0 = L0 MP1y - L1 MN1y, h1 = L1 MN1x - L0 MP1x, h2 = L2 fA1 - (h0 M1x + h1 M1y)
+  double gL[3][3];
+  double gM1x = 0.0, gM1y = 0.0, gMN1x = 0.0, gMN1y = 0.0, gMP1x = 0.0, gMP1y = 0.0;
+  double gfA1 = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const double h0 = L[i][0] * MP1y - L[i][1] * MN1y;
+    const double h1 = L[i][1] * MN1x - L[i][0] * MP1x;
+    const double g2 = gH[3 * i + 2];
+    const double g0 = gH[3 * i + 0] - g2 * M1x;
+    const double g1 = gH[3 * i + 1] - g2 * M1y;
+    gM1x -= g2 * h0;
+    gM1y -= g2 * h1;
+    gL[i][2] = g2 * fA1;
+    gfA1 += g2 * L[i][2];
+    gL[i][0] = g0 * MP1y - g1 * MP1x;
+    gL[i][1] = g1 * MN1x - g0 * MN1y;
+    gMP1y += g0 * L[i][0];
+    gMN1y -= g0 * L[i][1];
+    gMN1x += g1 * L[i][1];
+    gMP1x -= g1 * L[i][0];
+  }
+  // L = H_A2^-1 H_C
+  const double gmx = gL[0][2] - gL[0][0] - gL[0][1];
+  const double gmy = gL[1][2] - gL[1][0] - gL[1][1];
+  const double gc11 = gL[0][0] * N2x + gL[1][0] * N2y + gL[2][0];
+  const double gc22 = gL[0][1] * P2x + gL[1][1] * P2y + gL[2][1];
+  const double gc33 = gL[2][2] - gL[2][0] - gL[2][1] + gmx * M2x + gmy * M2y;
+  double gM2x = gmx * c33, gM2y = gmy * c33;
+  const double gN2x = gL[0][0] * c11, gN2y = gL[1][0] * c11;
+  const double gP2x = gL[0][1] * c22, gP2y = gL[1][1] * c22;
+  // core
+  const double gt1 = gc11 * Q3y * Q4x + gc22 * Q3x * Q4y;
+  const double gt2 = gc33 * Q3x * Q3y;
+  const double gQ3x = gc22 * t1 * Q4y + gc33 * t2 * Q3y - gt1;
+  const double gQ3y = gc11 * t1 * Q4x + gc33 * t2 * Q3x - gt1;
+  const double gQ4x = gc11 * t1 * Q3y - gt2;
+  const double gQ4y = gc22 * t1 * Q3x - gt2;
+  gfA1 += gt1;
+  const double gfA2 = gt2;
+  // signed areas: source side
+  gMN1x += gfA1 * MP1y + gQ3y * MQ1y;
+  gMN1y += -gfA1 * MP1x - gQ3y * MQ1x;
+  gMP1x += -gfA1 * MN1y - gQ3x * MQ1y;
+  gMP1y += gfA1 * MN1x + gQ3x * MQ1x;
+  const double gMQ1x = gQ3x * MP1y - gQ3y * MN1y;
+  const double gMQ1y = gQ3y * MN1x - gQ3x * MP1x;
+  // target side
+  const double gMN2x = gfA2 * MP2y + gQ4y * MQ2y;
+  const double gMN2y = -gfA2 * MP2x - gQ4y * MQ2x;
+  const double gMP2x = -gfA2 * MN2y - gQ4x * MQ2y;
+  const double gMP2y = gfA2 * MN2x + gQ4x * MQ2x;
+  const double gMQ2x = gQ4x * MP2y - gQ4y * MN2y;
+  const double gMQ2y = gQ4y * MN2x - gQ4x * MP2x;
+  // difference vectors
+  gs[0] = gM1x - gMN1x - gMP1x - gMQ1x;
+  gs[1] = gM1y - gMN1y - gMP1y - gMQ1y;
+  gs[2] = gMN1x;
+  gs[3] = gMN1y;
+  gs[4] = gMP1x;
+  gs[5] = gMP1y;
+  gs[6] = gMQ1x;
+  gs[7] = gMQ1y;
+  gM2x -= gMN2x + gMP2x + gMQ2x;
+  gM2y -= gMN2y + gMP2y + gMQ2y;
+  gd[0] = gM2x;
+  gd[1] = gM2y;
+  gd[2] = gN2x + gMN2x;
+  gd[3] = gN2y + gMN2y;
+  gd[4] = gP2x + gMP2x;
+  gd[5] = gP2y + gMP2y;
+  gd[6] = gMQ2x;
+  gd[7] = gMQ2y;
 }
 
 // Doubled signed areas (MNP, MQP, MNQ, NPQ) of one side, as in ACA.

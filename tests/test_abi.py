@@ -90,6 +90,18 @@ def test_sk_frame_host_setup(lib):
     assert np.array_equal(np.array(list(frame)).reshape(3, 3), ref)
 
 
+def test_general_aca_validation(lib):
+    assert lib.hg_aca_fwd(FAKE, FAKE, -1, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_fwd(None, FAKE, 4, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_fwd(FAKE, FAKE, 4, None, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_fwd(None, None, 0, None, None) == _abi.HG_OK
+    assert lib.hg_aca_bwd(FAKE, FAKE, FAKE, -1, FAKE, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_bwd(FAKE, FAKE, None, 4, FAKE, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_bwd(FAKE, FAKE, FAKE, 4, None, None, None) == _abi.HG_EINVAL
+    assert b"NULL" in lib.hg_last_error()
+    assert lib.hg_aca_bwd(None, None, None, 0, None, None, None) == _abi.HG_OK
+
+
 def test_ransac_validation(lib):
     f = lib.hg_ransac
     ws_need = lib.hg_ransac_ws_bytes(2000, 4096)

@@ -143,3 +143,58 @@ def test_config4_full_batch_sampled():
     assert np.isfinite(L).all() and np.isfinite(g).all()
     idx = np.random.default_rng(1).choice(1024, 32, replace=False)
     compare_oracle(pb, L[idx], g[idx], idx, "config4")
+
+
+@pytest.mark.parametrize("B", [1, 3, 257, 1000])
+def test_general_aca_forward_backward(B):
+    """General quadrilaterals: H at ACA's own scale equal to the oracle's
+    tensorised ACA (float64), and the reverse mode to both point sets within
+    float rounding of float64 autograd."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    src, dst, _ = synth.quadruples(B, 40 + B)
+    s32, d32 = np.ascontiguousarray(src.T), np.ascontiguousarray(dst.T)
+    s, d = torch.from_numpy(s32).cuda(), torch.from_numpy(d32).cuda()
+    announce(f"aca general fwd/bwd B={B}")
+    H = hgpu.hg_aca_fwd(s, d).cpu().numpy().reshape(B, 3, 3)
+    s64, d64 = torch.from_numpy(s32.astype(np.float64)), torch.from_numpy(d32.astype(np.float64))
+    Hr = ow.h_aca(s64, d64).numpy()
+    assert (np.abs(H - Hr).max(axis=(1, 2)) <= 1e-12 * np.abs(Hr).max(axis=(1, 2))).all()
+    rng = np.random.default_rng(B)
+    gH = rng.normal(size=(B, 9))
+    gs, gd = hgpu.hg_aca_bwd(s, d, torch.from_numpy(gH).cuda())
+    gsr, gdr = ow.aca_vjp(s64, d64, torch.from_numpy(gH).reshape(B, 3, 3))
+    g = np.concatenate([gs.cpu().numpy(), gd.cpu().numpy()], axis=1)
+    gr = np.concatenate([gsr.numpy(), gdr.numpy()], axis=1)
+    assert rel(g, gr).max() < 1e-6
+    # one side only
+    _, gd2 = hgpu.hg_aca_bwd(s, d, torch.from_numpy(gH).cuda(), want_src=False)
+    torch.cuda.synchronize()
+    assert torch.equal(gd2.cpu(), gd.cpu())
+
+
+def test_general_aca_in_the_photometric_pipeline():
+    """With the square's corners as the source quadrilateral, the general solver
+    gives the same loss and offset gradient as the rectangle solver (the loss
+    does not depend on the scale of H), and both match float64 autograd
+    through the DLT solve."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    pb = synth.patches(16, 23, size=64, sigma=3.0, max_shift=8, max_offset=12.0)
+    # offsets on a 2^-10 grid, so corner + offset is exact in float32 as in double
+    pb.offsets = (np.round(pb.offsets * 1024.0) / 1024.0).astype(np.float32)
+    corners = ow.square_corners(64, torch.float32).numpy()          # TL TR BR BL
+    mnpq = [0, 1, 3, 2]                                               # -> M N P Q
+    src = torch.from_numpy(np.tile(corners[mnpq].reshape(1, 8), (16, 1))).cuda()
+    off = torch.from_numpy(pb.offsets).cuda().requires_grad_(True)
+    img = torch.from_numpy(pb.img).cuda()
+    tgt = torch.from_numpy(pb.tgt).cuda()
+    announce("aca general in the warp-l1 pipeline, 16 patches 64x64")
+    dst = (src.reshape(16, 4, 2) + off[:, mnpq]).reshape(16, 8)
+    L = hgpu.WarpL1.apply(hgpu.ACAGeneral.apply(src, dst), img, tgt)
+    (g,) = torch.autograd.grad(L.sum(), off)
+    Lr_, gr_ = run_pipeline(pb)
+    L, g = L.detach().cpu().numpy(), g.cpu().numpy()
+    assert np.allclose(L, Lr_, rtol=1e-6, atol=0)
+    assert rel(g, gr_).max() < 1e-5
+    compare_oracle(pb, L, g, slice(None), "general ACA 64x64")

@@ -165,3 +165,21 @@ def loss_fd_grad(offsets, img, tgt, h=1e-6, solver=h_dlt):
                 e[:, k, c] = h
                 g[:, k, c] = (loss(off + e, im, tg, solver) - loss(off - e, im, tg, solver)) / (2 * h)
     return g
+
+
+def refine_ref(offsets, img, tgt, iters, step, solver=h_dlt):
+    """Iterative refinement of float32 offsets (B, 4, 2): each iteration takes
+    every patch's float64 loss gradient at the current offsets, rounds it to
+    float32 and sets offsets = offsets - step * gradient in float32 (the
+    network's predicted update of an iterative deep homography pipeline
+    replaced by a gradient step). Returns (offsets float32, loss float64 at
+    the final offsets)."""
+    import numpy as np
+    off = np.array(offsets, dtype=np.float32, copy=True)
+    st = np.float32(step)
+    for _ in range(iters):
+        _, g = loss_and_grad(off.astype(np.float64), img, tgt, solver)
+        off = off - st * g.numpy().astype(np.float32)
+    L = loss(torch.as_tensor(off, dtype=torch.float64), torch.as_tensor(img, dtype=torch.float64),
+             torch.as_tensor(tgt, dtype=torch.float64), solver)
+    return off, L.detach()

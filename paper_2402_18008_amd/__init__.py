@@ -267,15 +267,13 @@ class AdaptiveRansac:
         return self
 
 
-class RansacGraph:
-    def __init__(self, br, tune=None, stream=None):
-        t = _tuning(tune)
-        h = C.c_void_p()
-        _abi.call("hg_ransac_batched_graph_create", br.corr.data_ptr(), br.ld, br.off.data_ptr(),
-                  br.n_pairs, br.n_hyp, br.thresh, br.seed, None if t is None else C.byref(t),
-                  *br._args(), _stream(stream), C.byref(h))
-        self.h = h
-        self.owner = br          # keeps the captured buffers alive
+class Graph:
+    """A captured launch sequence (hg_graph); ``owner`` keeps the captured
+    buffers alive for as long as the graph exists."""
+
+    def __init__(self, handle, owner):
+        self.h = handle
+        self.owner = owner
 
     def launch(self, stream=None):
         _abi.call("hg_graph_launch", self.h, _stream(stream))
@@ -290,6 +288,18 @@ class RansacGraph:
             self.close()
         except Exception:
             pass
+
+
+class RansacGraph(Graph):
+    """hg_ransac_batched captured for replay (the BatchedRansac's buffers)."""
+
+    def __init__(self, br, tune=None, stream=None):
+        t = _tuning(tune)
+        h = C.c_void_p()
+        _abi.call("hg_ransac_batched_graph_create", br.corr.data_ptr(), br.ld, br.off.data_ptr(),
+                  br.n_pairs, br.n_hyp, br.thresh, br.seed, None if t is None else C.byref(t),
+                  *br._args(), _stream(stream), C.byref(h))
+        super().__init__(h, br)
 
 
 # ---- differentiable 4-point-offset pipeline ----------------------------------
@@ -474,3 +484,40 @@ def photometric_loss(offsets, img, tgt):
     h, w = img.shape[-2:]
     H = ACARect.apply(offsets, 0.0, 0.0, float(w - 1), float(w - 1) / float(h - 1))
     return WarpL1.apply(H, img, tgt)
+
+
+class Refine:
+    """Iterative refinement of 4-point offsets (hg_refine): ``iters`` rounds
+    of Algorithm 1 -> warp + L1 backward -> reverse mode -> offsets -= step *
+    grad on h x w patches. Owns its workspace; ``run()`` launches eagerly,
+    ``graph()`` captures the same sequence for replay. ``offsets`` (B, 4, 2)
+    float32 is updated in place; ``loss`` (B,) holds the final loss."""
+
+    def __init__(self, img, tgt, offsets, iters=6, step=1.0, with_loss=True):
+        _img3(img, "img")
+        _img3(tgt, "tgt")
+        self.img, self.tgt = img, tgt
+        self.offsets = _c(offsets, "offsets")
+        self.B, self.h, self.w = img.shape
+        if tuple(offsets.shape) != (self.B, 4, 2) or tuple(tgt.shape) != tuple(img.shape):
+            raise ValueError("shapes: img, tgt (B, h, w); offsets (B, 4, 2)")
+        self.iters, self.step = int(iters), float(step)
+        self.loss = torch.empty(self.B, dtype=torch.float32, device=img.device) if with_loss else None
+        nb = _abi.lib().hg_refine_ws_bytes(self.B)
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=img.device)
+        self.nb = nb
+
+    def _args(self):
+        return (self.img.data_ptr(), self.tgt.data_ptr(), self.B, self.h, self.w, self.iters,
+                self.step, self.offsets.data_ptr(),
+                self.loss.data_ptr() if self.loss is not None else None,
+                self.ws.data_ptr(), self.nb)
+
+    def run(self, stream=None):
+        _abi.call("hg_refine", *self._args(), _stream(stream))
+        return self.offsets, self.loss
+
+    def graph(self, stream=None):
+        h = C.c_void_p()
+        _abi.call("hg_refine_graph_create", *self._args(), _stream(stream), C.byref(h))
+        return Graph(h, self)

@@ -54,3 +54,47 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 int device_cus();
 
 }  // namespace hg
+
+// A captured sequence of launches, replayed by hg_graph_launch.
+struct hg_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace hg {
+
+// Captures what record(stream) launches into a new graph. The caller's stream
+// is drained first; capture runs on a private non-blocking stream.
+template <class Record>
+int capture_graph(void *caller_stream, Record &&record, hg_graph **out) {
+  *out = nullptr;
+  HG_HIP(hipStreamSynchronize(as_stream(caller_stream)));
+  hipStream_t cap;
+  HG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hg_graph *g = new hg_graph{nullptr, nullptr};
+  int st = HG_OK;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    st = fail(HG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  } else {
+    st = record(cap);
+    e = hipStreamEndCapture(cap, &g->graph);
+    if (st == HG_OK && e != hipSuccess)
+      st = fail(HG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (st == HG_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(HG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  (void)hipStreamDestroy(cap);
+  if (st != HG_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return HG_OK;
+}
+
+}  // namespace hg

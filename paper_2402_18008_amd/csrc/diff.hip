@@ -542,6 +542,101 @@ __global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__res
   }
 }
 
+// Iterative refinement of the offsets (the six-solve structure of iterative
+// deep homography networks, with the network's predicted update replaced by a
+// gradient step on the photometric loss): per iteration Algorithm 1, the warp
+// + L1 backward, Algorithm 1's reverse mode and off -= step * grad.
+__global__ void fill_kernel(float *__restrict__ p, int n, float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void step_kernel(float *__restrict__ off, const float *__restrict__ g, int n,
+                            float step) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) off[i] = off[i] - step * g[i];
+}
+
+struct RefineArgs {
+  const float *img, *tgt;
+  int B, h, w, iters;
+  float step;
+  float *off, *loss;
+  double *H, *gH;
+  float *goff, *ones;
+};
+
+constexpr size_t kWsAlign = 256;
+inline size_t round_up(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+static size_t refine_ws_bytes(int B) {
+  const size_t b = static_cast<size_t>(B);
+  return 2 * round_up(b * 9 * sizeof(double)) + round_up(b * 8 * sizeof(float)) +
+         round_up(b * sizeof(float));
+}
+
+static int launch_refine(const RefineArgs &a, hipStream_t s) {
+  // the rectangle as hg_aca_rect_fwd receives it (its aspect ratio rounded to float)
+  const double x0 = 0.0, y0 = 0.0, w = a.w - 1;
+  const double r = static_cast<double>(static_cast<float>(double(a.w - 1) / double(a.h - 1)));
+  const dim3 small((a.B + 255) / 256), threads(256);
+  hipLaunchKernelGGL(fill_kernel, small, threads, 0, s, a.ones, a.B, 1.0f);
+  if (int st = launched("fill_kernel")) return st;
+  for (int it = 0; it < a.iters; ++it) {
+    hipLaunchKernelGGL(rect_fwd_kernel, small, threads, 0, s, a.off, a.B, x0, y0, w, r, a.H);
+    hipLaunchKernelGGL(warp_bwd_kernel<false>, dim3(a.B), dim3(kDiffThreads), 0, s, a.H, a.img,
+                       a.tgt, a.ones, nullptr, a.h, a.w, a.gH);
+    hipLaunchKernelGGL(rect_bwd_kernel, small, threads, 0, s, a.off, a.gH, a.B, x0, y0, w, r,
+                       a.goff);
+    hipLaunchKernelGGL(step_kernel, dim3((8 * a.B + 255) / 256), threads, 0, s, a.off, a.goff,
+                       8 * a.B, a.step);
+    if (int st = launched("refinement iteration")) return st;
+  }
+  if (a.loss) {
+    hipLaunchKernelGGL(rect_fwd_kernel, small, threads, 0, s, a.off, a.B, x0, y0, w, r, a.H);
+    hipLaunchKernelGGL(warp_fwd_kernel<0>, dim3(a.B), dim3(kDiffThreads), 0, s, a.H, a.img, a.tgt,
+                       a.h, a.w, a.loss, nullptr);
+    if (int st = launched("refinement loss")) return st;
+  }
+  return HG_OK;
+}
+
+static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
+                       int32_t iters, float step, float *offsets, float *loss, void *ws,
+                       size_t ws_bytes, const char *fn, RefineArgs &a) {
+  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(h >= 2 && w >= 2 && h <= 32768 && w <= 32768, "%s: image size %d x %d out of range",
+             fn, h, w);
+  HG_REQUIRE(iters >= 0 && iters <= 1000, "%s: iters = %d outside [0, 1000]", fn, iters);
+  HG_REQUIRE(std::isfinite(step), "%s: step is not finite", fn);
+  HG_REQUIRE(B <= (1 << 24), "%s: B = %d above 2^24", fn, B);
+  if (B > 0) {
+    HG_REQUIRE(img && tgt && offsets, "%s: NULL img, tgt or offsets", fn);
+    if (!ws || ws_bytes < refine_ws_bytes(B) || !aligned(ws, kWsAlign))
+      return fail(HG_EWORKSPACE, "%s: workspace of %zu bytes (256-byte aligned) needed, got %zu",
+                  fn, refine_ws_bytes(B), ws ? ws_bytes : size_t(0));
+  }
+  a.img = img;
+  a.tgt = tgt;
+  a.B = B;
+  a.h = h;
+  a.w = w;
+  a.iters = iters;
+  a.step = step;
+  a.off = offsets;
+  a.loss = loss;
+  char *p = static_cast<char *>(ws);
+  const size_t b = static_cast<size_t>(B);
+  a.H = reinterpret_cast<double *>(p);
+  p += round_up(b * 9 * sizeof(double));
+  a.gH = reinterpret_cast<double *>(p);
+  p += round_up(b * 9 * sizeof(double));
+  a.goff = reinterpret_cast<float *>(p);
+  p += round_up(b * 8 * sizeof(float));
+  a.ones = reinterpret_cast<float *>(p);
+  return HG_OK;
+}
+
 static int check_rect(float w, float r, int B, const char *fn) {
   HG_REQUIRE(B >= 0, "%s: B < 0", fn);
   HG_REQUIRE(std::isfinite(w) && w > 0.0f && std::isfinite(r) && r > 0.0f,
@@ -668,4 +763,33 @@ extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const fl
   hipLaunchKernelGGL(warp_bwd_kernel<true>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H,
                      img, nullptr, nullptr, grad_warped, h, w, grad_H);
   return launched("warp_bwd_kernel<stored>");
+}
+
+extern "C" size_t hg_refine_ws_bytes(int32_t B) { return B > 0 ? refine_ws_bytes(B) : 0; }
+
+extern "C" int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
+                         int32_t iters, float step, float *offsets, float *loss, void *ws,
+                         size_t ws_bytes, void *stream) {
+  clear_error();
+  RefineArgs a;
+  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss, ws, ws_bytes,
+                           "hg_refine", a))
+    return st;
+  if (B == 0) return HG_OK;
+  return launch_refine(a, as_stream(stream));
+}
+
+extern "C" int hg_refine_graph_create(const float *img, const float *tgt, int32_t B, int32_t h,
+                                      int32_t w, int32_t iters, float step, float *offsets,
+                                      float *loss, void *ws, size_t ws_bytes, void *stream,
+                                      hg_graph **out) {
+  clear_error();
+  HG_REQUIRE(out, "hg_refine_graph_create: NULL out");
+  *out = nullptr;
+  RefineArgs a;
+  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss, ws, ws_bytes,
+                           "hg_refine_graph_create", a))
+    return st;
+  HG_REQUIRE(B > 0, "hg_refine_graph_create: B must be > 0");
+  return capture_graph(stream, [&](hipStream_t cap) { return launch_refine(a, cap); }, out);
 }

@@ -957,11 +957,6 @@ extern "C" int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *
   return launch_batched(a, t, ws, as_stream(stream));
 }
 
-struct hg_graph {
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-};
-
 extern "C" int hg_ransac_batched_graph_create(const float *corr, int64_t ld, const int64_t *off,
                                               int32_t n_pairs, int32_t n_hyp, float thresh,
                                               uint64_t seed, const hg_ransac_tuning *tune,
@@ -978,34 +973,8 @@ extern "C" int hg_ransac_batched_graph_create(const float *corr, int64_t ld, con
   const hg_ransac_tuning t = tune ? *tune : lookup_tune(n_pairs, n_hyp);
   RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp, t.hyps_per_block, thresh, seed,
                            best_H, best_count, best_hyp, inlier_mask, hyp_counts);
-  // let pending work on the caller's stream finish before capturing elsewhere
-  HG_HIP(hipStreamSynchronize(as_stream(stream)));
-  hipStream_t cap;
-  HG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hg_graph *g = new hg_graph{nullptr, nullptr};
-  int st = HG_OK;
-  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    st = fail(HG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
-  } else {
-    st = launch_batched(a, t, ws, cap);
-    e = hipStreamEndCapture(cap, &g->graph);
-    if (st == HG_OK && e != hipSuccess)
-      st = fail(HG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    if (st == HG_OK) {
-      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) st = fail(HG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    }
-  }
-  (void)hipStreamDestroy(cap);
-  if (st != HG_OK) {
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
-    delete g;
-    return st;
-  }
-  *out = g;
-  return HG_OK;
+  return capture_graph(stream, [&](hipStream_t cap) { return launch_batched(a, t, ws, cap); },
+                       out);
 }
 
 extern "C" int hg_graph_launch(hg_graph *g, void *stream) {

@@ -198,3 +198,50 @@ def test_general_aca_in_the_photometric_pipeline():
     assert np.allclose(L, Lr_, rtol=1e-6, atol=0)
     assert rel(g, gr_).max() < 1e-5
     compare_oracle(pb, L, g, slice(None), "general ACA 64x64")
+
+
+def _refine_case():
+    pb = synth.patches(8, 31, size=48, sigma=3.0, max_shift=4, max_offset=6.0)
+    rng = np.random.default_rng(0)
+    true = np.repeat(-pb.shift[:, None, :].astype(np.float32), 4, axis=1)
+    off0 = (true + rng.uniform(-1.5, 1.5, true.shape)).astype(np.float32)
+    return pb, off0
+
+
+def test_refine_against_oracle_and_graph_replays():
+    """Six refinement iterations (solve, warp + L1 backward, reverse mode,
+    step) against the oracle's loop; the captured graph replays the eager
+    result bit for bit, with the offsets reset by eager work between
+    replays."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    pb, off0 = _refine_case()
+    img = torch.from_numpy(pb.img).cuda()
+    tgt = torch.from_numpy(pb.tgt).cuda()
+    off = torch.from_numpy(off0).cuda()
+    announce("refine eager B=8 48x48 iters=6")
+    R = hgpu.Refine(img, tgt, off, iters=6, step=20.0)
+    R.run()
+    torch.cuda.synchronize()
+    o_gpu, L_gpu = off.cpu().numpy(), R.loss.cpu().numpy()
+    o_ref, L_ref = ow.refine_ref(off0, pb.img, pb.tgt, 6, 20.0)
+    assert np.abs(o_gpu - o_ref).max() < 1e-4, np.abs(o_gpu - o_ref).max()
+    assert np.allclose(L_gpu, L_ref.numpy(), rtol=1e-5, atol=0)
+    announce("refine graph replays")
+    G = R.graph()
+    for _ in range(3):
+        off.copy_(torch.from_numpy(off0))
+        torch.cuda.synchronize()
+        G.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(off.cpu().numpy(), o_gpu)
+        assert np.array_equal(R.loss.cpu().numpy(), L_gpu)
+    G.close()
+    # zero iterations: offsets untouched, loss at the start
+    off.copy_(torch.from_numpy(off0))
+    R0 = hgpu.Refine(img, tgt, off, iters=0, step=20.0)
+    R0.run()
+    L0 = hgpu.photometric_loss(off, img, tgt)
+    torch.cuda.synchronize()
+    assert np.array_equal(off.cpu().numpy(), off0)
+    assert torch.equal(R0.loss, L0)

@@ -195,6 +195,28 @@ int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_
                        int32_t *best_hyp, uint8_t *inlier_mask, int32_t *n_evaluated, void *ws,
                        size_t ws_bytes, void *stream);
 
+/* ---- n-point refit on inliers (HO-SVD) ------------------------------------
+ * Least-squares homography of each pair over the points whose mask byte is
+ * non-zero (all points when mask is NULL), by the HO-SVD method that the paper
+ * recommends for n points (Sec. 3.5): both sides normalised about their
+ * centroids with RMS distance sqrt(2), the first two rows of H eliminated in
+ * the least-squares sense, the last row h3 minimising ||A h|| / ||h3||
+ * (smallest eigenvector of the 3 x 3 reduced Gram matrix, cyclic Jacobi),
+ * all in double precision; then denormalised.
+ *   corr, ld, off  as hg_ransac_batched (points [off[p], off[p+1]) of the
+ *                  planes x1 y1 x2 y2); H maps (x1, y1) to (x2, y2).
+ *   mask           off[n_pairs] bytes (e.g. hg_ransac_batched's inlier mask)
+ *                  or NULL.
+ *   H              n_pairs x 9 floats (output), scaled as hg_solve4.
+ *   n_used         n_pairs int32 (output, may be NULL): points used.
+ *   flags          n_pairs bytes (output, may be NULL): bit2 = fewer than 4
+ *                  points or a singular normalised system; H written as 0.
+ * One workgroup per pair (suited to sets of up to ~10^5 points).
+ * Errors: n_pairs < 0, NULL corr/off/H with n_pairs > 0, ld < 1 ->
+ * HG_EINVAL. n_pairs == 0 is a no-op.                                       */
+int hg_refit_ho(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
+                const uint8_t *mask, float *H, int32_t *n_used, uint8_t *flags, void *stream);
+
 /* Times every supported tuning on the given problem (allocates temporary
  * outputs, synchronises the stream) and stores the fastest in *out and in the
  * process-wide cache used when tune == NULL; also written to the JSON file

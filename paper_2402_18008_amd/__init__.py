@@ -182,6 +182,28 @@ def _tuning(tune):
     return Tuning(*(int(v) for v in tune), *([0] * (4 - len(tune))))
 
 
+def hg_refit_ho(corr, off, mask=None, H=None, n_used=None, flags=None, stream=None):
+    """HO-SVD least-squares homography per pair over the masked points.
+    corr (4, total) float32 planes x1 y1 x2 y2, off (n_pairs + 1,) int64 on
+    the device, mask (total,) uint8 or None (all points). Returns (H
+    (n_pairs, 9) float32, n_used (n_pairs,) int32, flags (n_pairs,) uint8)."""
+    ld, total = _corr_planes(corr)
+    _dev(off, "off", torch.int64)
+    n_pairs = off.numel() - 1
+    dev = corr.device
+    if mask is not None:
+        _dev(mask, "mask", torch.uint8)
+        if mask.numel() < total:
+            raise ValueError("mask must cover every point")
+    H = torch.empty((n_pairs, 9), dtype=torch.float32, device=dev) if H is None else H
+    n_used = torch.empty(n_pairs, dtype=torch.int32, device=dev) if n_used is None else n_used
+    flags = torch.empty(n_pairs, dtype=torch.uint8, device=dev) if flags is None else flags
+    _abi.call("hg_refit_ho", corr.data_ptr(), ld, off.data_ptr(), n_pairs,
+              mask.data_ptr() if mask is not None else None, H.data_ptr(), n_used.data_ptr(),
+              flags.data_ptr(), _stream(stream))
+    return H, n_used, flags
+
+
 class BatchedRansac:
     """Device buffers and launcher for RANSAC over many uneven pairs.
 

@@ -52,6 +52,7 @@ SIGNATURES = {
     "hg_ransac_batched_graph_create": (C.c_int, [vp, i64, vp, i32, i32, f32, u64,
                                                  C.POINTER(Tuning), vp, vp, vp, vp, vp, vp, sz,
                                                  vp, C.POINTER(vp)]),
+    "hg_refit_ho": (C.c_int, [vp, i64, vp, i32, vp, vp, vp, vp, vp]),
     "hg_graph_launch": (C.c_int, [vp, vp]),
     "hg_graph_destroy": (None, [vp]),
     "hg_aca_rect_fwd": (C.c_int, [vp, i32, f32, f32, f32, f32, vp, vp]),

@@ -1,0 +1,286 @@
+// n-point homography refit on RANSAC inliers by the HO-SVD reduction (the
+// paper's recommendation for n points): both sides are normalised about their
+// centroids with an isotropic scale giving RMS distance sqrt(2); the first
+// two rows of H are eliminated in the least-squares sense, leaving the last
+// row h3 as the right singular vector of the 2n x 3 matrix
+//   M = [(I - P) D_u X ; (I - P) D_v X],   X = [x y 1], P = X (X^T X)^-1 X^T,
+// and h1 = (X^T X)^-1 X^T D_u X h3, h2 likewise with D_v.
+//
+// One workgroup per pair: pass 1 sums the selected points' coordinates (the
+// centroids), pass 2 sums 29 moments of the centred coordinates in double;
+// the normalisation enters afterwards as powers of the two scales. One lane
+// then forms the 3 x 3 Gram matrix
+//   M^T M = S2u - S1u S0^-1 S1u + S2v - S1v S0^-1 S1v
+// (S0 = X^T X, S1u = X^T D_u X, S2u = X^T D_u^2 X), takes its eigenvector of
+// smallest eigenvalue by cyclic Jacobi rotations, recovers h1, h2,
+// denormalises and writes the power-of-two scaled float H. Points are read
+// twice; the second pass of a pair of RANSAC size hits L2.
+#include <cmath>
+
+#include "common.hpp"
+#include "solver_dev.hpp"
+
+namespace hg {
+
+constexpr int kRefitThreads = 256;
+constexpr int kMoments = 29;   // S0: 5 (n counted in pass 1), S1u, S2u, S1v, S2v: 6 each
+
+// Workgroup sum of NV doubles; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void refit_block_sum(double (&v)[NV]) {
+  __shared__ double red[kRefitThreads / 64][NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[k] = x;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wv][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = red[0][k];
+#pragma unroll
+      for (int w = 1; w < kRefitThreads / 64; ++w) s += red[w][k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Symmetric 3 x 3 from the six monomial sums m = {xx, xy, x, yy, y, 1} with
+// the scales a (source) applied as X = [a x, a y, 1] and a factor f.
+__host__ __device__ __forceinline__ void sym3(const double *m, double a, double f, double S[3][3]) {
+  S[0][0] = f * a * a * m[0];
+  S[0][1] = S[1][0] = f * a * a * m[1];
+  S[0][2] = S[2][0] = f * a * m[2];
+  S[1][1] = f * a * a * m[3];
+  S[1][2] = S[2][1] = f * a * m[4];
+  S[2][2] = f * m[5];
+}
+
+__host__ __device__ __forceinline__ bool inverse3(const double A[3][3], double Ai[3][3]) {
+  const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+  if (!(fabs(det) > 0.0) || !(fabs(det) <= 1.7976931348623157e308)) return false;
+  const double r = 1.0 / det;
+  Ai[0][0] = c00 * r;
+  Ai[1][0] = c01 * r;
+  Ai[2][0] = c02 * r;
+  Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * r;
+  Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * r;
+  Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * r;
+  Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * r;
+  Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * r;
+  Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * r;
+  return true;
+}
+
+__host__ __device__ __forceinline__ void matmul3(const double A[3][3], const double B[3][3],
+                                        double C[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[i][j] = A[i][0] * B[0][j] + A[i][1] * B[1][j] + A[i][2] * B[2][j];
+}
+
+// Cyclic Jacobi eigenvalue iteration on a symmetric 3 x 3 (Golub and Van
+// Loan, Sec. 8.5): each rotation zeroes one off-diagonal entry; V collects the
+// rotations (eigenvectors in its columns). Returns the column of the smallest
+// eigenvalue in v.
+__host__ __device__ inline void smallest_eigvec3(double A[3][3], double v[3]) {
+  double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (!(off > 1e-36 * dia)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = A[p][q];
+      if (apq == 0.0) continue;
+      // rotation (c, s) with t = tan: t^2 + 2 tau t - 1 = 0, the smaller root
+      const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {   // A <- A J (columns p, q)
+        const double akp = A[k][p], akq = A[k][q];
+        A[k][p] = c * akp - s * akq;
+        A[k][q] = s * akp + c * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {   // A <- J^T A (rows p, q)
+        const double apk = A[p][k], aqk = A[q][k];
+        A[p][k] = c * apk - s * aqk;
+        A[q][k] = s * apk + c * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {   // V <- V J
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][q] = s * vkp + c * vkq;
+      }
+    }
+  }
+  int m = 0;
+  if (A[1][1] < A[m][m]) m = 1;
+  if (A[2][2] < A[m][m]) m = 2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = V[k][m];
+}
+
+// The per-pair solve from the centred moments m (layout of refit_kernel's
+// pass 2), the count n and the centroids: H (row-major, double) = T2^-1 Hn T1,
+// or zeros when X^T X is singular.
+__host__ __device__ inline void refit_solve(const double *m, double n, double cx, double cy,
+                                            double cu, double cv, double *h) {
+  // scales: RMS distance sqrt(2) on each side
+  const double sa = sqrt(2.0 * n / (m[0] + m[3]));
+  const double sb = sqrt(2.0 * n / (m[16] + m[28]));
+  const double m0[6] = {m[0], m[1], m[2], m[3], m[4], n};
+  double S0[3][3], S1u[3][3], S2u[3][3], S1v[3][3], S2v[3][3], S0i[3][3];
+  sym3(m0, sa, 1.0, S0);
+  sym3(m + 5, sa, sb, S1u);
+  sym3(m + 11, sa, sb * sb, S2u);
+  sym3(m + 17, sa, sb, S1v);
+  sym3(m + 23, sa, sb * sb, S2v);
+  bool ok = inverse3(S0, S0i);
+  if (ok) {
+    double Tu[3][3], Tv[3][3], Pu[3][3], Pv[3][3];
+    matmul3(S0i, S1u, Tu);   // S0^-1 S1u
+    matmul3(S0i, S1v, Tv);
+    matmul3(S1u, Tu, Pu);    // S1u S0^-1 S1u
+    matmul3(S1v, Tv, Pv);
+    double C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) C[i][j] = (S2u[i][j] - Pu[i][j]) + (S2v[i][j] - Pv[i][j]);
+    // symmetrise against rounding
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 3; ++j) C[i][j] = C[j][i] = 0.5 * (C[i][j] + C[j][i]);
+    double h3[3];
+    smallest_eigvec3(C, h3);
+    double Hn[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Hn[0][j] = Tu[j][0] * h3[0] + Tu[j][1] * h3[1] + Tu[j][2] * h3[2];
+      Hn[1][j] = Tv[j][0] * h3[0] + Tv[j][1] * h3[1] + Tv[j][2] * h3[2];
+      Hn[2][j] = h3[j];
+    }
+    // H = T2^-1 Hn T1, T1 = [[sa, 0, -sa cx], [0, sa, -sa cy], [0, 0, 1]],
+    // T2^-1 = [[1/sb, 0, cu], [0, 1/sb, cv], [0, 0, 1]]
+    const double T1[3][3] = {{sa, 0.0, -sa * cx}, {0.0, sa, -sa * cy}, {0.0, 0.0, 1.0}};
+    const double T2i[3][3] = {{1.0 / sb, 0.0, cu}, {0.0, 1.0 / sb, cv}, {0.0, 0.0, 1.0}};
+    double A[3][3], Hd[3][3];
+    matmul3(T2i, Hn, A);
+    matmul3(A, T1, Hd);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = Hd[i / 3][i % 3];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kRefitThreads) void refit_kernel(
+    const float *__restrict__ corr, int64_t ld, const int64_t *__restrict__ off,
+    const uint8_t *__restrict__ mask, float *__restrict__ Hout, int32_t *__restrict__ n_used,
+    uint8_t *__restrict__ flags) {
+  const int p = blockIdx.x;
+  // the pair's range, clamped into the planes
+  const int64_t a = min(max(off[p], int64_t(0)), ld);
+  const int64_t b = min(max(off[p + 1], a), ld);
+  const float *X1 = corr, *Y1 = corr + ld, *X2 = corr + 2 * ld, *Y2 = corr + 3 * ld;
+  __shared__ double cen[5];
+  // pass 1: count and centroids
+  double s1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = a + threadIdx.x; i < b; i += kRefitThreads) {
+    if (mask && !mask[i]) continue;
+    s1[0] += 1.0;
+    s1[1] += static_cast<double>(X1[i]);
+    s1[2] += static_cast<double>(Y1[i]);
+    s1[3] += static_cast<double>(X2[i]);
+    s1[4] += static_cast<double>(Y2[i]);
+  }
+  refit_block_sum(s1);
+  if (threadIdx.x == 0) {
+    const double n = s1[0];
+#pragma unroll
+    for (int k = 1; k < 5; ++k) s1[k] = n > 0.0 ? s1[k] / n : 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) cen[k] = s1[k];
+  }
+  __syncthreads();
+  const double n = cen[0];
+  const int used = static_cast<int>(n);
+  if (used < 4) {   // uniform across the workgroup
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Hout[9 * p + k] = 0.0f;
+      if (n_used) n_used[p] = used;
+      if (flags) flags[p] = static_cast<uint8_t>(kZeroH);
+    }
+    return;
+  }
+  const double cx = cen[1], cy = cen[2], cu = cen[3], cv = cen[4];
+  // pass 2: moments of the centred coordinates; monomials {xx, xy, x, yy, y, 1}
+  double m[kMoments];
+#pragma unroll
+  for (int k = 0; k < kMoments; ++k) m[k] = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += kRefitThreads) {
+    if (mask && !mask[i]) continue;
+    const double x = static_cast<double>(X1[i]) - cx, y = static_cast<double>(Y1[i]) - cy;
+    const double u = static_cast<double>(X2[i]) - cu, v = static_cast<double>(Y2[i]) - cv;
+    const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
+    const double uu = u * u, vv = v * v;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m[k] += mono[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      m[5 + k] += u * mono[k];
+      m[11 + k] += uu * mono[k];
+      m[17 + k] += v * mono[k];
+      m[23 + k] += vv * mono[k];
+    }
+  }
+  refit_block_sum(m);
+  if (threadIdx.x != 0) return;
+  double h[9];
+  refit_solve(m, n, cx, cy, cu, cv, h);
+  float hf[9];
+  const uint32_t f = scale_to_float(h, hf);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Hout[9 * p + k] = hf[k];
+  if (n_used) n_used[p] = used;
+  if (flags) flags[p] = static_cast<uint8_t>(f);
+}
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" int hg_refit_ho(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
+                           const uint8_t *mask, float *H, int32_t *n_used, uint8_t *flags,
+                           void *stream) {
+  clear_error();
+  HG_REQUIRE(n_pairs >= 0, "hg_refit_ho: n_pairs = %d < 0", n_pairs);
+  if (n_pairs == 0) return HG_OK;
+  HG_REQUIRE(corr && off && H, "hg_refit_ho: NULL corr, off or H");
+  HG_REQUIRE(ld >= 1 && ld <= (INT64_MAX / 8), "hg_refit_ho: ld = %lld out of range",
+             static_cast<long long>(ld));
+  hipLaunchKernelGGL(refit_kernel, dim3(n_pairs), dim3(kRefitThreads), 0, as_stream(stream), corr,
+                     ld, off, mask, H, n_used, flags);
+  return launched("refit_kernel");
+}

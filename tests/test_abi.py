@@ -130,6 +130,16 @@ def test_refine_validation(lib):
     assert not out.value
 
 
+def test_refit_validation(lib):
+    f = lib.hg_refit_ho
+    assert f(FAKE, 10, FAKE, -1, None, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(None, 10, FAKE, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(FAKE, 10, None, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(FAKE, 10, FAKE, 2, None, None, None, None, None) == _abi.HG_EINVAL
+    assert f(FAKE, 0, FAKE, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
+    assert f(None, 0, None, 0, None, None, None, None, None) == _abi.HG_OK
+
+
 def test_ransac_validation(lib):
     f = lib.hg_ransac
     ws_need = lib.hg_ransac_ws_bytes(2000, 4096)

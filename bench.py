@@ -8,8 +8,9 @@ whole batch, inputs resident in HBM before timing starts.
 
 The JSON line also carries the roofline of the solver kernel, the CPU oracle
 timed on a bounded sample of the same workload, and secondary measurements of
-the other stages of the path (SKS, small-batch latency, RANSAC scoring,
-batched RANSAC, the differentiable pipeline) when those are built.
+the other stages of the path (SKS, small-batch latency, the three-point affine,
+the simplified SK, RANSAC scoring, batched and adaptive RANSAC, the
+differentiable pipeline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -121,6 +122,47 @@ def cpu_baseline(src, dst, n_sample, workers):
                        f"({cpu_s:.1f} s of CPU time, {wall:.2f} s wall)")
 
 
+SK_BYTES = 32 + 36 + 1            # 8 fp32 in, 9 fp32 out, 1 flag byte
+AFFINE_BYTES = 48 + 24 + 1        # 12 fp32 in, 6 fp32 out, 1 flag byte
+
+
+def bench_sk(stream, n, workers, steps=20, warmup=3):
+    """Simplified SK: n images of one pattern, one launch."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2402_18008_amd as hgpu
+    log(f"simplified SK: generating {n} pattern images")
+    D = torch.from_numpy(synth.pattern_images(n, 1, workers=workers)).cuda()
+    H = torch.empty((9, n), dtype=torch.float32, device=D.device)
+    F = torch.empty(n, dtype=torch.uint8, device=D.device)
+    obj = [float(v) for v in synth.PATTERN]
+    t, p = time_launches(lambda: hgpu.hg_solve_sk(obj, D, H=H, flags=F), steps, warmup, stream)
+    k = float(np.mean(p))
+    return {"sk_simplified": {"n": n, "homographies_per_s": n / (t / steps * 1e-3),
+                              "kernel_ms": k, "bytes_per_unit": SK_BYTES,
+                              "GBps": SK_BYTES * n / (k * 1e-3) / 1e9,
+                              "frac_hbm": SK_BYTES * n / (k * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def bench_affine(stream, S, D, steps=20, warmup=3):
+    """Three-point affine on the first three points of the quadruple batch."""
+    import numpy as np
+    import torch
+    import paper_2402_18008_amd as hgpu
+    n = S.shape[1]
+    A = torch.empty((6, n), dtype=torch.float32, device=S.device)
+    F = torch.empty(n, dtype=torch.uint8, device=S.device)
+    s6, d6 = S[:6], D[:6]
+    t, p = time_launches(lambda: hgpu.hg_solve3_affine(s6, d6, A=A, flags=F), steps, warmup,
+                         stream)
+    k = float(np.mean(p))
+    return {"affine3": {"n": n, "maps_per_s": n / (t / steps * 1e-3), "kernel_ms": k,
+                        "bytes_per_unit": AFFINE_BYTES,
+                        "GBps": AFFINE_BYTES * n / (k * 1e-3) / 1e9,
+                        "frac_hbm": AFFINE_BYTES * n / (k * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 FP32_FLOP_PER_HYP_PT = 21   # the division-free test as 21 FLOP (FMA = 2): 3 rows x 2 FMA,
                             # 2 FMA residuals, mul + FMA norm, (tau w)^2; the kernel folds
                             # tau into the operands and issues 12 VALU instructions
@@ -207,6 +249,13 @@ def bench_ransac_batched(stream):
     t, p = time_launches(lambda: ar.run((tune[0], 64, tune[2])), 20, 3, stream)
     ms_adaptive = float(np.median(p))
     n_eval = ar.n_evaluated.cpu().numpy()
+    # HO-SVD refit of every pair on the inlier mask the persistent kernel produced
+    br.run(tune)
+    Hr = torch.empty((br.n_pairs, 9), dtype=torch.float32, device="cuda")
+    ur = torch.empty(br.n_pairs, dtype=torch.int32, device="cuda")
+    fr = torch.empty(br.n_pairs, dtype=torch.uint8, device="cuda")
+    t, p = time_launches(lambda: hgpu.hg_refit_ho(corr, off, br.mask, Hr, ur, fr), 20, 3, stream)
+    ms_refit = float(np.median(p))
     rate = hyp_pts / (ms_graph * 1e-3)
     return {"ransac_batched_512x1024": {
         "hyp_pts": hyp_pts, "tuning": list(tune),
@@ -216,7 +265,9 @@ def bench_ransac_batched(stream):
         "fp32_tflops": FP32_FLOP_PER_HYP_PT * rate / 1e12,
         "fp32_frac_of_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_PEAK_TFLOPS,
         "adaptive_ms": ms_adaptive, "adaptive_mean_hyps_evaluated": float(n_eval.mean()),
-        "adaptive_hyp_pts": float((np.diff(cb.off) * n_eval).sum())}}
+        "adaptive_hyp_pts": float((np.diff(cb.off) * n_eval).sum()),
+        "refit_ho_ms": ms_refit, "refit_points": int(total),
+        "refit_points_per_s": total / (ms_refit * 1e-3)}}
 
 
 def bench_diff(stream):
@@ -261,9 +312,23 @@ def bench_diff(stream):
     t, p = time_launches(stored, 40, 4, stream)
     ms_s = float(np.median(p))
     min_bytes = 2 * B * S * S * 4          # img and tgt read once
-    return {"warp_l1_1024x128x128": {
+    out = {"warp_l1_1024x128x128": {
         "recompute_ms": ms_r, "stored_ms": ms_s, "patches_per_s": B / (ms_r * 1e-3),
         "effective_GBps": min_bytes / (ms_r * 1e-3) / 1e9, "speedup_vs_stored": ms_s / ms_r}}
+    # six-solve iterative refinement (solve, warp + L1 backward, reverse mode, step,
+    # then the final loss): eager launches against one graph replay
+    o = off.clone()
+    R = hgpu.Refine(img, tgt, o, iters=6, step=20.0)
+    t, p = time_launches(R.run, 20, 3, stream)
+    ms_e = float(np.median(p))
+    G = R.graph()
+    t, p = time_launches(G.launch, 20, 3, stream)
+    ms_g = float(np.median(p))
+    G.close()
+    out["refine_6iter_1024x128x128"] = {"eager_ms": ms_e, "graph_ms": ms_g,
+                                        "kernels_per_pass": 4 * 6 + 3,
+                                        "patches_per_s": B / (ms_g * 1e-3)}
+    return out
 
 
 def main():
@@ -273,7 +338,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 26, help="quadruples (default 2^26)")
     ap.add_argument("--part", default="all",
-                    choices=["all", "solver", "ransac", "batched", "diff"],
+                    choices=["all", "solver", "sk", "affine", "ransac", "batched", "diff"],
                     help="run only one stage (for profiler runs); the JSON line then carries "
                          "only that stage")
     ap.add_argument("--solver-only", action="store_true", help="same as --part solver")
@@ -306,6 +371,10 @@ def main():
 
     workers = max(1, min(args.gen_workers, os.cpu_count() or 1))
     n = args.n
+    if args.part == "sk":
+        print(json.dumps({"part": "sk", **bench_sk(stream, n, workers, args.steps,
+                                                   args.warmup)}), flush=True)
+        return
     log(f"generating {n} quadruples with {workers} processes")
     t0 = time.perf_counter()
     src, dst, lab = synth.quadruples_parallel(n, 1, degenerate_every=100, workers=workers)
@@ -316,6 +385,10 @@ def main():
     H = torch.empty((9, n), dtype=torch.float32, device=dev)
     F = torch.empty(n, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+    if args.part == "affine":
+        print(json.dumps({"part": "affine", **bench_affine(stream, S, D, args.steps,
+                                                           args.warmup)}), flush=True)
+        return
 
     def step():
         hgpu.hg_solve4(S, D, hgpu.HG_ACA, H=H, flags=F)
@@ -379,6 +452,8 @@ def main():
             t, p = time_launches(lambda: hgpu.hg_solve4(s4, d4, meth, H=h4, flags=f4), 200, 20,
                                  stream)
             extra[f"{name}_4096_us_per_launch"] = float(np.median(p) * 1e3)
+        extra.update(bench_affine(stream, S, D))
+        extra.update(bench_sk(stream, n, workers))
         extra.update(bench_ransac_single(stream))
         extra.update(bench_ransac_batched(stream))
         extra.update(bench_diff(stream))

@@ -285,30 +285,42 @@ int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t 
 int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const float *grad_loss,
                    int32_t B, int32_t h, int32_t w, double *grad_H, void *stream);
 
+/* Fused offsets -> loss and offsets -> gradient for h x w patches (h, w >= 2)
+ * whose source rectangle has its corners at the pixel centres: the same
+ * arithmetic as hg_aca_rect_fwd(offsets, 0, 0, w - 1, (w - 1) / (h - 1))
+ * followed by hg_warp_l1_fwd, resp. hg_warp_l1_bwd and hg_aca_rect_bwd, in
+ * one launch each (one workgroup per patch; Algorithm 1 and its reverse mode
+ * run in the workgroup's first lane, H stays on chip).
+ *   hg_photometric_fwd: loss (B floats).
+ *   hg_photometric_bwd: grad_offsets (B x 4 x 2 floats) = grad_loss[b] *
+ *     dloss[b]/d offsets_b.
+ * Errors: B < 0, h or w outside [2, 32768], NULL pointer with B > 0 ->
+ * HG_EINVAL; B == 0 is a no-op.                                            */
+int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt, int32_t B,
+                       int32_t h, int32_t w, float *loss, void *stream);
+int hg_photometric_bwd(const float *offsets, const float *img, const float *tgt,
+                       const float *grad_loss, int32_t B, int32_t h, int32_t w,
+                       float *grad_offsets, void *stream);
+
 /* Iterative refinement of 4-point offsets: the structure of iterative deep
  * homography networks (six solver calls per forward pass in the deep-pipeline
  * experiments), with the network's predicted update replaced by a gradient
- * step on the photometric loss. Each of `iters` iterations runs Algorithm 1
- * on the h x w patch rectangle (corners at the pixel centres, as
- * hg_aca_rect_fwd with x0 = y0 = 0, w - 1, (w - 1) / (h - 1)), the warp + L1
- * backward (hg_warp_l1_bwd with grad_loss = 1), Algorithm 1's reverse mode and
- *   offsets -= step * dL_b/d offsets_b      (float, per patch).
- * offsets (B x 4 x 2 floats, TL TR BR BL) are updated in place; loss (B floats,
- * may be NULL) receives the loss at the final offsets.
- * ws: caller-owned device workspace of hg_refine_ws_bytes(B) bytes, 256-byte
- * aligned (H, dL/dH, gradients). hg_refine launches 4 * iters + 1 (+ 2 with
- * loss) kernels on the stream; hg_refine_graph_create captures the same
+ * step on the photometric loss. Each of `iters` iterations is one launch of
+ * hg_photometric_bwd's kernel with grad_loss = 1 that also applies
+ *   offsets -= step * dL_b/d offsets_b      (float, per patch)
+ * in place. offsets: B x 4 x 2 floats, TL TR BR BL; loss (B floats, may be
+ * NULL) receives the loss at the final offsets (one more launch).
+ * hg_refine launches on the stream; hg_refine_graph_create captures the same
  * sequence (with these pointers and scalars) for hg_graph_launch (allocates,
  * synchronises; needs B > 0).
- * Errors: B < 0 or > 2^24, h or w outside [2, 32768], iters outside
- * [0, 1000], non-finite step, NULL pointer with B > 0 -> HG_EINVAL; missing,
- * small or misaligned workspace -> HG_EWORKSPACE. B == 0 is a no-op.       */
-size_t hg_refine_ws_bytes(int32_t B);
+ * Errors: B < 0, h or w outside [2, 32768], iters outside [0, 1000],
+ * non-finite step, NULL img/tgt/offsets with B > 0 -> HG_EINVAL. B == 0 is a
+ * no-op.                                                                   */
 int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w, int32_t iters,
-              float step, float *offsets, float *loss, void *ws, size_t ws_bytes, void *stream);
+              float step, float *offsets, float *loss, void *stream);
 int hg_refine_graph_create(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
-                           int32_t iters, float step, float *offsets, float *loss, void *ws,
-                           size_t ws_bytes, void *stream, hg_graph **out);
+                           int32_t iters, float step, float *offsets, float *loss, void *stream,
+                           hg_graph **out);
 
 /* Plain stored-intermediate form of the same pipeline (for comparison):
  * warp -> warped (B x h x w floats) ; L1 -> loss ; its backward ->

@@ -499,10 +499,53 @@ class WarpL1(torch.autograd.Function):
         return hg_warp_l1_bwd(H, img, tgt, gl), None, None
 
 
-def photometric_loss(offsets, img, tgt):
+def hg_photometric_fwd(offsets, img, tgt, stream=None):
+    """Fused offsets (B, 4, 2) -> per-patch loss (B,) (Algorithm 1 + warp + L1)."""
+    _c(offsets, "offsets")
+    B, h, w = _img3(img, "img")
+    _img3(tgt, "tgt")
+    loss = torch.empty(B, dtype=torch.float32, device=img.device)
+    _abi.call("hg_photometric_fwd", offsets.data_ptr(), img.data_ptr(), tgt.data_ptr(), B, h, w,
+              loss.data_ptr(), _stream(stream))
+    return loss
+
+
+def hg_photometric_bwd(offsets, img, tgt, grad_loss, stream=None):
+    """Fused gradient: grad_loss[b] * dloss_b/d offsets_b, (B, 4, 2) float32."""
+    _c(offsets, "offsets")
+    B, h, w = _img3(img, "img")
+    _img3(tgt, "tgt")
+    _c(grad_loss, "grad_loss")
+    g = torch.empty((B, 4, 2), dtype=torch.float32, device=img.device)
+    _abi.call("hg_photometric_bwd", offsets.data_ptr(), img.data_ptr(), tgt.data_ptr(),
+              grad_loss.data_ptr(), B, h, w, g.data_ptr(), _stream(stream))
+    return g
+
+
+class PhotometricL1(torch.autograd.Function):
+    """offsets -> per-patch loss in one fused launch; backward in one fused
+    launch that recomputes H, the warp and Algorithm 1's reverse mode."""
+
+    @staticmethod
+    def forward(ctx, offsets, img, tgt):
+        offsets, img, tgt = offsets.contiguous(), img.contiguous(), tgt.contiguous()
+        ctx.save_for_backward(offsets, img, tgt)
+        return hg_photometric_fwd(offsets, img, tgt)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        offsets, img, tgt = ctx.saved_tensors
+        gl = grad_loss.to(torch.float32).contiguous()
+        return hg_photometric_bwd(offsets, img, tgt, gl), None, None
+
+
+def photometric_loss(offsets, img, tgt, fused=True):
     """Per-patch loss of the 4-point-offset pipeline for h x w patches with
     corners at the pixel centres (0, 0) .. (w-1, h-1); differentiable in
-    offsets."""
+    offsets. ``fused=False`` composes the separate ACARect and WarpL1 stages
+    (same arithmetic, four launches instead of two)."""
+    if fused:
+        return PhotometricL1.apply(offsets, img, tgt)
     h, w = img.shape[-2:]
     H = ACARect.apply(offsets, 0.0, 0.0, float(w - 1), float(w - 1) / float(h - 1))
     return WarpL1.apply(H, img, tgt)
@@ -511,7 +554,7 @@ def photometric_loss(offsets, img, tgt):
 class Refine:
     """Iterative refinement of 4-point offsets (hg_refine): ``iters`` rounds
     of Algorithm 1 -> warp + L1 backward -> reverse mode -> offsets -= step *
-    grad on h x w patches. Owns its workspace; ``run()`` launches eagerly,
+    grad on h x w patches (one fused launch per iteration); ``run()`` launches eagerly,
     ``graph()`` captures the same sequence for replay. ``offsets`` (B, 4, 2)
     float32 is updated in place; ``loss`` (B,) holds the final loss."""
 
@@ -525,15 +568,11 @@ class Refine:
             raise ValueError("shapes: img, tgt (B, h, w); offsets (B, 4, 2)")
         self.iters, self.step = int(iters), float(step)
         self.loss = torch.empty(self.B, dtype=torch.float32, device=img.device) if with_loss else None
-        nb = _abi.lib().hg_refine_ws_bytes(self.B)
-        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=img.device)
-        self.nb = nb
 
     def _args(self):
         return (self.img.data_ptr(), self.tgt.data_ptr(), self.B, self.h, self.w, self.iters,
                 self.step, self.offsets.data_ptr(),
-                self.loss.data_ptr() if self.loss is not None else None,
-                self.ws.data_ptr(), self.nb)
+                self.loss.data_ptr() if self.loss is not None else None)
 
     def run(self, stream=None):
         _abi.call("hg_refine", *self._args(), _stream(stream))

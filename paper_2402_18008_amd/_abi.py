@@ -59,9 +59,10 @@ SIGNATURES = {
     "hg_aca_rect_bwd": (C.c_int, [vp, vp, i32, f32, f32, f32, f32, vp, vp]),
     "hg_aca_fwd": (C.c_int, [vp, vp, i32, vp, vp]),
     "hg_aca_bwd": (C.c_int, [vp, vp, vp, i32, vp, vp, vp]),
-    "hg_refine_ws_bytes": (sz, [i32]),
-    "hg_refine": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp, sz, vp]),
-    "hg_refine_graph_create": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp, sz, vp,
+    "hg_photometric_fwd": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, vp]),
+    "hg_photometric_bwd": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, vp, vp]),
+    "hg_refine": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp]),
+    "hg_refine_graph_create": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp,
                                          C.POINTER(vp)]),
     "hg_warp_l1_fwd": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, vp]),
     "hg_warp_l1_bwd": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, vp, vp]),

@@ -69,13 +69,11 @@ __global__ void rect_fwd_kernel(const float *__restrict__ off, int B, double x0,
   for (int i = 0; i < 9; ++i) H[9 * b + i] = h[i];
 }
 
-// Reverse mode through Algorithm 1 (each step's adjoint in reverse order).
-__global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__restrict__ gH, int B,
-                                double x0, double y0, double w, double r,
-                                float *__restrict__ goff) {
-  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= B) return;
-  const RectCorners k = rect_targets(off + 8 * bi, x0, y0, w, r);
+// Reverse mode through Algorithm 1 (each step's adjoint in reverse order) for
+// one patch: offsets o (8), dL/dH gHb (9) -> dL/d offsets (8, order TL TR BR BL).
+__device__ __forceinline__ void rect_bwd_one(const float *o, const double *gHb, double x0,
+                                             double y0, double w, double r, double *gout) {
+  const RectCorners k = rect_targets(o, x0, y0, w, r);
   const double d1[3] = {k.N2x - k.M2x, k.P2x - k.M2x, k.Q2x - k.M2x};
   const double d2[3] = {k.N2y - k.M2y, k.P2y - k.M2y, k.Q2y - k.M2y};
   const double c0 = d1[1] * d2[2] - d1[2] * d2[1];
@@ -85,9 +83,9 @@ __global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__r
   double g1[3], g2[3], g3[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    g1[i] = gH[9 * bi + 3 * i + 0];
-    g2[i] = gH[9 * bi + 3 * i + 1];
-    g3[i] = gH[9 * bi + 3 * i + 2];
+    g1[i] = gHb[3 * i + 0];
+    g2[i] = gHb[3 * i + 1];
+    g3[i] = gHb[3 * i + 2];
   }
   double gb[3], gM2x = 0, gM2y = 0, gN2x = 0, gN2y = 0, gP2x = 0, gP2y = 0, gQ2x = 0, gQ2y = 0;
   // h3 = w b - x0 h1 - y0 h2
@@ -138,15 +136,26 @@ __global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__r
   gP2y += gd2[1];
   gQ2y += gd2[2];
   gM2y -= gd2[0] + gd2[1] + gd2[2];
-  float *g = goff + 8 * bi;   // TL TR BR BL = M N Q P
-  g[0] = static_cast<float>(gM2x);
-  g[1] = static_cast<float>(gM2y);
-  g[2] = static_cast<float>(gN2x);
-  g[3] = static_cast<float>(gN2y);
-  g[4] = static_cast<float>(gQ2x);
-  g[5] = static_cast<float>(gQ2y);
-  g[6] = static_cast<float>(gP2x);
-  g[7] = static_cast<float>(gP2y);
+  // TL TR BR BL = M N Q P
+  gout[0] = gM2x;
+  gout[1] = gM2y;
+  gout[2] = gN2x;
+  gout[3] = gN2y;
+  gout[4] = gQ2x;
+  gout[5] = gQ2y;
+  gout[6] = gP2x;
+  gout[7] = gP2y;
+}
+
+__global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__restrict__ gH, int B,
+                                double x0, double y0, double w, double r,
+                                float *__restrict__ goff) {
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= B) return;
+  double g[8];
+  rect_bwd_one(off + 8 * bi, gH + 9 * bi, x0, y0, w, r, g);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) goff[8 * bi + i] = static_cast<float>(g[i]);
 }
 
 // adj(H) (cyclic cofactor form) scaled by 2^-e so that max|G| is in [0.5, 1);
@@ -332,18 +341,16 @@ __device__ __forceinline__ void sample_pos(const double *G, double x, double y, 
   sy = q1 * iq2;
 }
 
+// One patch b per workgroup; Hb: its 9 entries of H (global or LDS).
 // MODE 0: loss only; 2: stored warp only (rounded to float).
 template <int MODE>
-__global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__restrict__ H,
-                                                                const float *__restrict__ img,
-                                                                const float *__restrict__ tgt,
-                                                                int h, int w,
-                                                                float *__restrict__ loss,
-                                                                float *__restrict__ warped) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__restrict__ img,
+                                               const float *__restrict__ tgt, int h, int w, int b,
+                                               float *__restrict__ loss,
+                                               float *__restrict__ warped) {
   double G[9];
   int e;
-  load_G(H + 9 * b, G, e);
+  load_G(Hb, G, e);
   const int P = h * w;
   const float *I = img + static_cast<int64_t>(b) * P;
   const float *T = (MODE == 0) ? tgt + static_cast<int64_t>(b) * P : nullptr;
@@ -382,6 +389,16 @@ __global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__restrict__ H,
+                                                                const float *__restrict__ img,
+                                                                const float *__restrict__ tgt,
+                                                                int h, int w,
+                                                                float *__restrict__ loss,
+                                                                float *__restrict__ warped) {
+  warp_fwd_block<MODE>(H + 9 * blockIdx.x, img, tgt, h, w, blockIdx.x, loss, warped);
+}
+
 // dL/dH from dL/dG (G = 2^-e adj(H)), thread 0, double precision.
 __device__ __forceinline__ void adjugate_backward(const double *Hd, const double gG[9], int e,
                                                   double *gHout) {
@@ -403,22 +420,22 @@ __device__ __forceinline__ void adjugate_backward(const double *Hd, const double
   for (int i = 0; i < 9; ++i) gHout[i] = gH[i / 3][i % 3];
 }
 
-// FROM_STORED = false: recompute r = I_w - T and use sign(r) grad_loss / (h w);
+// One patch b per workgroup; Hb: its 9 entries of H (global or LDS); thread 0
+// writes dL/dH to gHout (9 doubles).
+// FROM_STORED = false: recompute r = I_w - T and use sign(r) gl, gl = grad_loss / (h w);
 // FROM_STORED = true: read dL/dI_w from grad_warped.
 template <bool FROM_STORED>
-__global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
-    const double *__restrict__ H, const float *__restrict__ img, const float *__restrict__ tgt,
-    const float *__restrict__ grad_loss, const float *__restrict__ grad_warped, int h, int w,
-    double *__restrict__ grad_H) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__restrict__ img,
+                                               const float *__restrict__ tgt, double gl,
+                                               const float *__restrict__ grad_warped, int h,
+                                               int w, int b, double *gHout) {
   double G[9];
   int e;
-  load_G(H + 9 * b, G, e);
+  load_G(Hb, G, e);
   const int P = h * w;
   const float *I = img + static_cast<int64_t>(b) * P;
   const float *T = FROM_STORED ? grad_warped + static_cast<int64_t>(b) * P
                                : tgt + static_cast<int64_t>(b) * P;
-  const double gl = FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(P);
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   PixelWalk pw(w);
   for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
@@ -465,7 +482,73 @@ __global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
   }
   double gG[9];
   block_sum<9>(acc, gG);
-  if (threadIdx.x == 0) adjugate_backward(H + 9 * b, gG, e, grad_H + 9 * b);
+  if (threadIdx.x == 0) adjugate_backward(Hb, gG, e, gHout);
+}
+
+template <bool FROM_STORED>
+__global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
+    const double *__restrict__ H, const float *__restrict__ img, const float *__restrict__ tgt,
+    const float *__restrict__ grad_loss, const float *__restrict__ grad_warped, int h, int w,
+    double *__restrict__ grad_H) {
+  const int b = blockIdx.x;
+  const double gl =
+      FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(h * w);
+  warp_bwd_block<FROM_STORED>(H + 9 * b, img, tgt, gl, grad_warped, h, w, b, grad_H + 9 * b);
+}
+
+// ---- fused offsets -> loss and offsets -> gradient (one workgroup per patch) --
+// Algorithm 1 runs in thread 0 of the patch's workgroup into LDS, then the
+// warp; the backward also runs Algorithm 1's reverse mode in thread 0. The
+// arithmetic is that of the separate kernels, in the same order.
+struct RectArgs {
+  double x0, y0, w, r;
+};
+
+__device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, double *Hs) {
+  if (threadIdx.x == 0) {
+    double hh[9];
+    rect_aca(rect_targets(o, ra.x0, ra.y0, ra.w, ra.r), ra.x0, ra.y0, ra.w, ra.r, hh);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hs[i] = hh[i];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kDiffThreads) void photo_fwd_kernel(const float *__restrict__ off,
+                                                                 const float *__restrict__ img,
+                                                                 const float *__restrict__ tgt,
+                                                                 int h, int w, RectArgs ra,
+                                                                 float *__restrict__ loss) {
+  __shared__ double Hs[9];
+  rect_to_lds(off + 8 * blockIdx.x, ra, Hs);
+  warp_fwd_block<0>(Hs, img, tgt, h, w, blockIdx.x, loss, nullptr);
+}
+
+// grad_offsets = grad_loss[b] dL_b/d offsets_b; with STEP, instead
+// offsets_b -= step * float(dL_b/d offsets_b) in place (grad_loss = 1).
+template <bool STEP>
+__global__ __launch_bounds__(kDiffThreads) void photo_bwd_kernel(
+    float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
+    const float *__restrict__ grad_loss, int h, int w, RectArgs ra, float step,
+    float *__restrict__ goff) {
+  __shared__ double Hs[9];
+  __shared__ double gHs[9];
+  const int b = blockIdx.x;
+  rect_to_lds(off + 8 * b, ra, Hs);
+  const double gl = static_cast<double>(STEP ? 1.0f : grad_loss[b]) / static_cast<double>(h * w);
+  warp_bwd_block<false>(Hs, img, tgt, gl, nullptr, h, w, b, gHs);
+  if (threadIdx.x == 0) {
+    double g[8];
+    rect_bwd_one(off + 8 * b, gHs, ra.x0, ra.y0, ra.w, ra.r, g);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float gf = static_cast<float>(g[i]);
+      if (STEP)
+        off[8 * b + i] = off[8 * b + i] - step * gf;
+      else
+        goff[8 * b + i] = gf;
+    }
+  }
 }
 
 __global__ void l1_fwd_kernel(const float *__restrict__ warped, const float *__restrict__ tgt,
@@ -544,78 +627,51 @@ __global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__res
 
 // Iterative refinement of the offsets (the six-solve structure of iterative
 // deep homography networks, with the network's predicted update replaced by a
-// gradient step on the photometric loss): per iteration Algorithm 1, the warp
-// + L1 backward, Algorithm 1's reverse mode and off -= step * grad.
-__global__ void fill_kernel(float *__restrict__ p, int n, float v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-__global__ void step_kernel(float *__restrict__ off, const float *__restrict__ g, int n,
-                            float step) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) off[i] = off[i] - step * g[i];
-}
-
+// gradient step on the photometric loss): per iteration one fused launch runs
+// Algorithm 1, the warp + L1 backward, Algorithm 1's reverse mode and
+// off -= step * grad for every patch.
 struct RefineArgs {
   const float *img, *tgt;
   int B, h, w, iters;
   float step;
   float *off, *loss;
-  double *H, *gH;
-  float *goff, *ones;
 };
 
-constexpr size_t kWsAlign = 256;
-inline size_t round_up(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
-
-static size_t refine_ws_bytes(int B) {
-  const size_t b = static_cast<size_t>(B);
-  return 2 * round_up(b * 9 * sizeof(double)) + round_up(b * 8 * sizeof(float)) +
-         round_up(b * sizeof(float));
+// The patch rectangle as hg_aca_rect_fwd receives it from a caller that
+// passes w - 1 and (w - 1) / (h - 1) as floats.
+static RectArgs patch_rect(int h, int w) {
+  RectArgs ra;
+  ra.x0 = 0.0;
+  ra.y0 = 0.0;
+  ra.w = static_cast<double>(static_cast<float>(w - 1));
+  ra.r = static_cast<double>(static_cast<float>(double(w - 1) / double(h - 1)));
+  return ra;
 }
 
 static int launch_refine(const RefineArgs &a, hipStream_t s) {
-  // the rectangle as hg_aca_rect_fwd receives it (its aspect ratio rounded to float)
-  const double x0 = 0.0, y0 = 0.0, w = a.w - 1;
-  const double r = static_cast<double>(static_cast<float>(double(a.w - 1) / double(a.h - 1)));
-  const dim3 small((a.B + 255) / 256), threads(256);
-  hipLaunchKernelGGL(fill_kernel, small, threads, 0, s, a.ones, a.B, 1.0f);
-  if (int st = launched("fill_kernel")) return st;
+  const RectArgs ra = patch_rect(a.h, a.w);
   for (int it = 0; it < a.iters; ++it) {
-    hipLaunchKernelGGL(rect_fwd_kernel, small, threads, 0, s, a.off, a.B, x0, y0, w, r, a.H);
-    hipLaunchKernelGGL(warp_bwd_kernel<false>, dim3(a.B), dim3(kDiffThreads), 0, s, a.H, a.img,
-                       a.tgt, a.ones, nullptr, a.h, a.w, a.gH);
-    hipLaunchKernelGGL(rect_bwd_kernel, small, threads, 0, s, a.off, a.gH, a.B, x0, y0, w, r,
-                       a.goff);
-    hipLaunchKernelGGL(step_kernel, dim3((8 * a.B + 255) / 256), threads, 0, s, a.off, a.goff,
-                       8 * a.B, a.step);
-    if (int st = launched("refinement iteration")) return st;
+    hipLaunchKernelGGL(photo_bwd_kernel<true>, dim3(a.B), dim3(kDiffThreads), 0, s, a.off, a.img,
+                       a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
+    if (int st = launched("photo_bwd_kernel<step>")) return st;
   }
   if (a.loss) {
-    hipLaunchKernelGGL(rect_fwd_kernel, small, threads, 0, s, a.off, a.B, x0, y0, w, r, a.H);
-    hipLaunchKernelGGL(warp_fwd_kernel<0>, dim3(a.B), dim3(kDiffThreads), 0, s, a.H, a.img, a.tgt,
-                       a.h, a.w, a.loss, nullptr);
-    if (int st = launched("refinement loss")) return st;
+    hipLaunchKernelGGL(photo_fwd_kernel, dim3(a.B), dim3(kDiffThreads), 0, s, a.off, a.img, a.tgt,
+                       a.h, a.w, ra, a.loss);
+    if (int st = launched("photo_fwd_kernel")) return st;
   }
   return HG_OK;
 }
 
 static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
-                       int32_t iters, float step, float *offsets, float *loss, void *ws,
-                       size_t ws_bytes, const char *fn, RefineArgs &a) {
+                       int32_t iters, float step, float *offsets, float *loss, const char *fn,
+                       RefineArgs &a) {
   HG_REQUIRE(B >= 0, "%s: B < 0", fn);
   HG_REQUIRE(h >= 2 && w >= 2 && h <= 32768 && w <= 32768, "%s: image size %d x %d out of range",
              fn, h, w);
   HG_REQUIRE(iters >= 0 && iters <= 1000, "%s: iters = %d outside [0, 1000]", fn, iters);
   HG_REQUIRE(std::isfinite(step), "%s: step is not finite", fn);
-  HG_REQUIRE(B <= (1 << 24), "%s: B = %d above 2^24", fn, B);
-  if (B > 0) {
-    HG_REQUIRE(img && tgt && offsets, "%s: NULL img, tgt or offsets", fn);
-    if (!ws || ws_bytes < refine_ws_bytes(B) || !aligned(ws, kWsAlign))
-      return fail(HG_EWORKSPACE, "%s: workspace of %zu bytes (256-byte aligned) needed, got %zu",
-                  fn, refine_ws_bytes(B), ws ? ws_bytes : size_t(0));
-  }
+  if (B > 0) HG_REQUIRE(img && tgt && offsets, "%s: NULL img, tgt or offsets", fn);
   a.img = img;
   a.tgt = tgt;
   a.B = B;
@@ -625,15 +681,6 @@ static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h,
   a.step = step;
   a.off = offsets;
   a.loss = loss;
-  char *p = static_cast<char *>(ws);
-  const size_t b = static_cast<size_t>(B);
-  a.H = reinterpret_cast<double *>(p);
-  p += round_up(b * 9 * sizeof(double));
-  a.gH = reinterpret_cast<double *>(p);
-  p += round_up(b * 9 * sizeof(double));
-  a.goff = reinterpret_cast<float *>(p);
-  p += round_up(b * 8 * sizeof(float));
-  a.ones = reinterpret_cast<float *>(p);
   return HG_OK;
 }
 
@@ -765,15 +812,37 @@ extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const fl
   return launched("warp_bwd_kernel<stored>");
 }
 
-extern "C" size_t hg_refine_ws_bytes(int32_t B) { return B > 0 ? refine_ws_bytes(B) : 0; }
+extern "C" int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt,
+                                  int32_t B, int32_t h, int32_t w, float *loss, void *stream) {
+  clear_error();
+  if (int st = check_img(img, tgt, B, h, w, "hg_photometric_fwd")) return st;
+  HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_fwd: patches need h, w >= 2");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(offsets && loss, "hg_photometric_fwd: NULL offsets or loss");
+  hipLaunchKernelGGL(photo_fwd_kernel, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), offsets,
+                     img, tgt, h, w, patch_rect(h, w), loss);
+  return launched("photo_fwd_kernel");
+}
+
+extern "C" int hg_photometric_bwd(const float *offsets, const float *img, const float *tgt,
+                                  const float *grad_loss, int32_t B, int32_t h, int32_t w,
+                                  float *grad_offsets, void *stream) {
+  clear_error();
+  if (int st = check_img(img, tgt, B, h, w, "hg_photometric_bwd")) return st;
+  HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_bwd: patches need h, w >= 2");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(offsets && grad_loss && grad_offsets, "hg_photometric_bwd: NULL pointer");
+  hipLaunchKernelGGL(photo_bwd_kernel<false>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream),
+                     const_cast<float *>(offsets), img, tgt, grad_loss, h, w, patch_rect(h, w), 0.0f,
+                     grad_offsets);
+  return launched("photo_bwd_kernel");
+}
 
 extern "C" int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
-                         int32_t iters, float step, float *offsets, float *loss, void *ws,
-                         size_t ws_bytes, void *stream) {
+                         int32_t iters, float step, float *offsets, float *loss, void *stream) {
   clear_error();
   RefineArgs a;
-  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss, ws, ws_bytes,
-                           "hg_refine", a))
+  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss, "hg_refine", a))
     return st;
   if (B == 0) return HG_OK;
   return launch_refine(a, as_stream(stream));
@@ -781,13 +850,12 @@ extern "C" int hg_refine(const float *img, const float *tgt, int32_t B, int32_t 
 
 extern "C" int hg_refine_graph_create(const float *img, const float *tgt, int32_t B, int32_t h,
                                       int32_t w, int32_t iters, float step, float *offsets,
-                                      float *loss, void *ws, size_t ws_bytes, void *stream,
-                                      hg_graph **out) {
+                                      float *loss, void *stream, hg_graph **out) {
   clear_error();
   HG_REQUIRE(out, "hg_refine_graph_create: NULL out");
   *out = nullptr;
   RefineArgs a;
-  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss, ws, ws_bytes,
+  if (int st = make_refine(img, tgt, B, h, w, iters, step, offsets, loss,
                            "hg_refine_graph_create", a))
     return st;
   HG_REQUIRE(B > 0, "hg_refine_graph_create: B must be > 0");

@@ -408,10 +408,12 @@ __global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
 }
 
 // Resets keys, done counters and the queue, and ranks pairs by size (largest
-// first, ties by index): each thread ranks one pair against all sizes, staged
-// through LDS in tiles of kThreads.
+// first, ties by index). Pair q's sort key is (N_q << 32) | ~q, unique per
+// pair, so the rank of p (the number of larger keys) is a permutation of
+// 0 .. n_pairs - 1. Each thread ranks one pair against all keys, staged
+// through LDS in tiles of kThreads and compared two per 16-byte read.
 __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int rank) {
-  __shared__ uint32_t tile[kThreads];
+  __shared__ __attribute__((aligned(16))) unsigned long long tile[kThreads];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0 && a.queue) *a.queue = 0u;
   if (p < a.n_pairs) {
@@ -436,21 +438,24 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
     if (p < a.n_pairs) order[p] = p;
     return;
   }
-  int64_t b;
-  uint32_t np = 0u;
-  if (p < a.n_pairs) pair_range(a, p, b, np);
+  auto sort_key = [&](int q) {
+    int64_t b;
+    uint32_t n = 0u;
+    pair_range(a, q, b, n);
+    return (static_cast<unsigned long long>(n) << 32) | (0xFFFFFFFFu - static_cast<uint32_t>(q));
+  };
+  const unsigned long long kp = p < a.n_pairs ? sort_key(p) : ~0ull;
   int r = 0;
   for (int q0 = 0; q0 < a.n_pairs; q0 += kThreads) {
     const int q = q0 + threadIdx.x;
-    uint32_t nq = 0u;
-    if (q < a.n_pairs) pair_range(a, q, b, nq);
     __syncthreads();
-    tile[threadIdx.x] = nq;
+    tile[threadIdx.x] = q < a.n_pairs ? sort_key(q) : 0ull;   // 0: below every real key
     __syncthreads();
-    const int m = min(kThreads, a.n_pairs - q0);
-    for (int k = 0; k < m; ++k) {
-      const uint32_t v = tile[k];
-      r += (v > np) || (v == np && q0 + k < p);
+    const ulonglong2 *t2 = reinterpret_cast<const ulonglong2 *>(tile);
+#pragma unroll 8
+    for (int k = 0; k < kThreads / 2; ++k) {
+      const ulonglong2 v = t2[k];
+      r += (v.x > kp) + (v.y > kp);
     }
   }
   if (p < a.n_pairs) order[r] = p;

@@ -102,18 +102,14 @@ def test_general_aca_validation(lib):
     assert lib.hg_aca_bwd(None, None, None, 0, None, None, None) == _abi.HG_OK
 
 
-def test_refine_validation(lib):
-    nb = lib.hg_refine_ws_bytes(16)
-    assert nb >= 16 * (72 + 72 + 32 + 4)
-    ws = C.c_void_p(0x100000)
+def test_refine_and_photometric_validation(lib):
     f = lib.hg_refine
 
     def call(**kw):
-        a = dict(img=FAKE, tgt=FAKE, B=16, h=32, w=32, it=6, step=1.0, off=FAKE, loss=None,
-                 ws=ws, nb=nb)
+        a = dict(img=FAKE, tgt=FAKE, B=16, h=32, w=32, it=6, step=1.0, off=FAKE, loss=None)
         a.update(kw)
         return f(a["img"], a["tgt"], a["B"], a["h"], a["w"], a["it"], a["step"], a["off"],
-                 a["loss"], a["ws"], a["nb"], None)
+                 a["loss"], None)
 
     assert call(B=-1) == _abi.HG_EINVAL
     assert call(h=1) == _abi.HG_EINVAL
@@ -121,23 +117,19 @@ def test_refine_validation(lib):
     assert call(it=1001) == _abi.HG_EINVAL
     assert call(step=float("nan")) == _abi.HG_EINVAL
     assert call(off=None) == _abi.HG_EINVAL
-    assert call(nb=nb - 1) == _abi.HG_EWORKSPACE
-    assert call(ws=C.c_void_p(0x100010)) == _abi.HG_EWORKSPACE
-    assert call(B=0, img=None, tgt=None, off=None, ws=None, nb=0) == _abi.HG_OK
+    assert call(B=0, img=None, tgt=None, off=None) == _abi.HG_OK
     out = C.c_void_p()
-    assert lib.hg_refine_graph_create(FAKE, FAKE, 0, 32, 32, 6, 1.0, FAKE, None, ws, nb, None,
+    assert lib.hg_refine_graph_create(FAKE, FAKE, 0, 32, 32, 6, 1.0, FAKE, None, None,
                                       C.byref(out)) == _abi.HG_EINVAL
     assert not out.value
-
-
-def test_refit_validation(lib):
-    f = lib.hg_refit_ho
-    assert f(FAKE, 10, FAKE, -1, None, FAKE, None, None, None) == _abi.HG_EINVAL
-    assert f(None, 10, FAKE, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
-    assert f(FAKE, 10, None, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
-    assert f(FAKE, 10, FAKE, 2, None, None, None, None, None) == _abi.HG_EINVAL
-    assert f(FAKE, 0, FAKE, 2, None, FAKE, None, None, None) == _abi.HG_EINVAL
-    assert f(None, 0, None, 0, None, None, None, None, None) == _abi.HG_OK
+    pf, pb = lib.hg_photometric_fwd, lib.hg_photometric_bwd
+    assert pf(FAKE, FAKE, FAKE, -1, 32, 32, FAKE, None) == _abi.HG_EINVAL
+    assert pf(FAKE, FAKE, FAKE, 4, 1, 32, FAKE, None) == _abi.HG_EINVAL
+    assert pf(None, FAKE, FAKE, 4, 32, 32, FAKE, None) == _abi.HG_EINVAL
+    assert pf(FAKE, FAKE, FAKE, 4, 32, 32, None, None) == _abi.HG_EINVAL
+    assert pb(FAKE, FAKE, FAKE, None, 4, 32, 32, FAKE, None) == _abi.HG_EINVAL
+    assert pb(FAKE, FAKE, FAKE, FAKE, 4, 32, 32, None, None) == _abi.HG_EINVAL
+    assert pf(None, None, None, 0, 32, 32, None, None) == _abi.HG_OK
 
 
 def test_ransac_validation(lib):

@@ -60,13 +60,13 @@ def test_rect_forward_backward():
         assert hg.herr(H[b].reshape(3, 3), Hx) < 1e-12
 
 
-def run_pipeline(pb, idx=None):
+def run_pipeline(pb, idx=None, fused=True):
     import paper_2402_18008_amd as hgpu
     sel = slice(None) if idx is None else idx
     off = torch.from_numpy(pb.offsets[sel]).cuda().requires_grad_(True)
     img = torch.from_numpy(pb.img[sel]).cuda()
     tgt = torch.from_numpy(pb.tgt[sel]).cuda()
-    L = hgpu.photometric_loss(off, img, tgt)
+    L = hgpu.photometric_loss(off, img, tgt, fused=fused)
     (g,) = torch.autograd.grad(L.sum(), off)
     torch.cuda.synchronize()
     return L.detach().cpu().numpy(), g.cpu().numpy()
@@ -83,11 +83,12 @@ def compare_oracle(pb, L, g, idx, label):
     return el, eg
 
 
-def test_small_patches_against_oracle():
+@pytest.mark.parametrize("fused", [True, False])
+def test_small_patches_against_oracle(fused):
     require_gpu()
     pb = synth.patches(24, 21, size=64, sigma=3.0, max_shift=8, max_offset=12.0)
-    announce("warp-l1 fwd+bwd 24 patches 64x64")
-    L, g = run_pipeline(pb)
+    announce(f"warp-l1 fwd+bwd 24 patches 64x64 fused={fused}")
+    L, g = run_pipeline(pb, fused=fused)
     compare_oracle(pb, L, g, slice(None), "64x64")
     # finite differences of the float64 oracle agree with the same gradient
     fd = ow.loss_fd_grad(pb.offsets[:4], pb.img[:4], pb.tgt[:4], h=1e-6).numpy()
@@ -245,3 +246,27 @@ def test_refine_against_oracle_and_graph_replays():
     torch.cuda.synchronize()
     assert np.array_equal(off.cpu().numpy(), off0)
     assert torch.equal(R0.loss, L0)
+
+
+def test_fused_pipeline_equals_separate_stages():
+    """The fused offsets -> loss / gradient launches do the arithmetic of the
+    separate Algorithm 1, warp and reverse-mode kernels in the same order: the
+    results are identical, on square and non-square patches."""
+    require_gpu()
+    for B, h, w, seed in ((64, 128, 128, 4), (7, 37, 53, 5)):
+        rng = np.random.default_rng(seed)
+        img = torch.from_numpy(rng.normal(size=(B, h, w)).astype(np.float32)).cuda()
+        tgt = torch.from_numpy(rng.normal(size=(B, h, w)).astype(np.float32)).cuda()
+        o = rng.uniform(-8, 8, (B, 4, 2)).astype(np.float32)
+        announce(f"fused vs separate B={B} {h}x{w}")
+        res = []
+        for fused in (True, False):
+            off = torch.from_numpy(o).cuda().requires_grad_(True)
+            import paper_2402_18008_amd as hgpu
+            L = hgpu.photometric_loss(off, img, tgt, fused=fused)
+            gl = torch.from_numpy(rng.random(B).astype(np.float32)).cuda() if not res else res[0][2]
+            (g,) = torch.autograd.grad(L, off, gl)
+            torch.cuda.synchronize()
+            res.append((L.detach().cpu(), g.cpu(), gl))
+        assert torch.equal(res[0][0], res[1][0])
+        assert torch.equal(res[0][1], res[1][1])

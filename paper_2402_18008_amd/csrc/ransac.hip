@@ -140,6 +140,10 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
   }
 }
 
+// Full chunks of P points per lane, then (P = 16) chunks of 8, then one
+// masked tail chunk of 4 or 8 points per lane, so that a pair's last chunk
+// wastes at most a chunk of the smaller shape. Counts are integer sums over
+// the points, so the result does not depend on the chunking.
 template <int P>
 __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
                                            const float (*Hs)[9], uint64_t vmask, int nh,
@@ -147,10 +151,20 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   constexpr uint32_t kChunk = kWaves * 64 * P;
+  constexpr uint32_t kChunk8 = kWaves * 64 * 8, kChunk4 = kWaves * 64 * 4;
   uint32_t c0 = 0;
   for (; c0 + kChunk <= n; c0 += kChunk)
     score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
-  if (c0 < n) score_chunk<P, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+  if (P > 8) {
+    for (; c0 + kChunk8 <= n; c0 += kChunk8)
+      score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+  }
+  if (c0 < n) {
+    if (n - c0 <= kChunk4)
+      score_chunk<4, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+    else
+      score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+  }
 }
 
 // Adaptive stopping rule: with eps = best_count / n, enough samples have been

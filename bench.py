@@ -323,6 +323,19 @@ def bench_diff(stream):
         "fused_ms": ms_f, "recompute_ms": ms_r, "stored_ms": ms_s,
         "patches_per_s": B / (ms_f * 1e-3),
         "effective_GBps": min_bytes / (ms_f * 1e-3) / 1e9, "speedup_vs_stored": ms_s / ms_f}}
+    # general-quadrilateral ACA and its reverse mode over 2^20 problems (one thread each)
+    src, dst, _ = synth.quadruples(1 << 20, 9)
+    S4 = torch.from_numpy(np.ascontiguousarray(src.T)).cuda()
+    D4 = torch.from_numpy(np.ascontiguousarray(dst.T)).cuda()
+    gH4 = torch.ones((1 << 20, 9), dtype=torch.float64, device="cuda")
+    t, p = time_launches(lambda: hgpu.hg_aca_fwd(S4, D4), 20, 3, stream)
+    ms_af = float(np.median(p))
+    t, p = time_launches(lambda: hgpu.hg_aca_bwd(S4, D4, gH4), 20, 3, stream)
+    ms_ab = float(np.median(p))
+    nq = 1 << 20
+    out["aca_general_2p20"] = {"fwd_ms": ms_af, "bwd_ms": ms_ab,
+                               "fwd_GBps": nq * (64 + 72) / (ms_af * 1e-3) / 1e9,
+                               "bwd_GBps": nq * (64 + 72 + 64) / (ms_ab * 1e-3) / 1e9}
     # six-solve iterative refinement (solve, warp + L1 backward, reverse mode, step,
     # then the final loss): eager launches against one graph replay
     o = off.clone()

@@ -101,7 +101,9 @@ __host__ __device__ inline void smallest_eigvec3(double A[3][3], double v[3]) {
   for (int sweep = 0; sweep < 32; ++sweep) {
     const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
     const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (!(off > 1e-36 * dia)) break;
+    // converged when the off-diagonal mass is at the rounding level of the
+    // diagonal (eps^2 ~ 5e-32): further sweeps cannot reduce it
+    if (!(off > 1e-30 * dia)) break;
 #pragma unroll
     for (int pq = 0; pq < 3; ++pq) {
       const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;

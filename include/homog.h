@@ -201,7 +201,7 @@ int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_
  * recommends for n points (Sec. 3.5): both sides normalised about their
  * centroids with RMS distance sqrt(2), the first two rows of H eliminated in
  * the least-squares sense, the last row h3 minimising ||A h|| / ||h3||
- * (smallest eigenvector of the 3 x 3 reduced Gram matrix, cyclic Jacobi),
+ * (smallest eigenvector of the 3 x 3 reduced Gram matrix),
  * all in double precision; then denormalised.
  *   corr, ld, off  as hg_ransac_batched (points [off[p], off[p+1]) of the
  *                  planes x1 y1 x2 y2); H maps (x1, y1) to (x2, y2).

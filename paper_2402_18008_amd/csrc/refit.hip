@@ -7,7 +7,8 @@
 // and h1 = (X^T X)^-1 X^T D_u X h3, h2 likewise with D_v.
 //
 // One workgroup per pair: pass 1 sums the selected points' coordinates (the
-// centroids), pass 2 sums 29 moments of the centred coordinates in double;
+// centroids), pass 2 sums 29 moments of the centred coordinates in double
+// (both in batches of 8 points per thread, loads issued ahead of use);
 // the normalisation enters afterwards as powers of the two scales. One lane
 // then forms the 3 x 3 Gram matrix
 //   M^T M = S2u - S1u S0^-1 S1u + S2v - S1v S0^-1 S1v
@@ -24,6 +25,33 @@ namespace hg {
 
 constexpr int kRefitThreads = 256;
 constexpr int kMoments = 29;   // S0: 5 (n counted in pass 1), S1u, S2u, S1v, S2v: 6 each
+
+// Points are visited kBatch at a time per thread (i0 + j * kRefitThreads),
+// all their loads issued before any is used: one memory round trip per batch
+// instead of one per point. A thread's points keep their order, so the sums
+// do not depend on kBatch.
+constexpr int kBatch = 8;
+
+struct PointBatch {
+  float x1[kBatch], y1[kBatch], x2[kBatch], y2[kBatch];
+  bool sel[kBatch];   // the point exists and its mask byte is set
+};
+
+__device__ __forceinline__ void load_batch(const float *X1, const float *Y1, const float *X2,
+                                           const float *Y2, const uint8_t *mask, int64_t i0,
+                                           int64_t b, PointBatch &pb) {
+#pragma unroll
+  for (int j = 0; j < kBatch; ++j) {
+    const int64_t i = i0 + static_cast<int64_t>(j) * kRefitThreads;
+    const bool in = i < b;
+    const int64_t ic = in ? i : b - 1;   // i0 < b, so every load stays inside the pair
+    pb.x1[j] = X1[ic];
+    pb.y1[j] = Y1[ic];
+    pb.x2[j] = X2[ic];
+    pb.y2[j] = Y2[ic];
+    pb.sel[j] = in && (!mask || mask[ic] != 0);
+  }
+}
 
 // Workgroup sum of NV doubles; the result is valid in thread 0.
 template <int NV>
@@ -140,6 +168,80 @@ __host__ __device__ inline void smallest_eigvec3(double A[3][3], double v[3]) {
   for (int k = 0; k < 3; ++k) v[k] = V[k][m];
 }
 
+// Eigenvector of the smallest eigenvalue of a symmetric positive
+// semi-definite 3 x 3 C. Its adjugate has the same eigenvectors with the
+// eigenvalues l2 l3, l1 l3 and l1 l2 (0 <= l1 <= l2 <= l3), so the wanted
+// vector is adj(C)'s dominant one. Repeated squaring of adj(C) (rescaled to
+// max |entry| = 1 each time) squares the ratio l1 / l2 at every step, so the
+// matrix becomes rank one, every column parallel to the wanted vector; the
+// column of largest norm is taken once it stops changing direction. If that
+// does not happen within 12 squarings (l1 within ~0.1 % of l2: a
+// near-degenerate problem) the Jacobi iteration decides.
+__host__ __device__ inline void smallest_eigvec3_adj(const double C[3][3], double v[3]) {
+  double A[3][3];
+  A[0][0] = C[1][1] * C[2][2] - C[1][2] * C[2][1];
+  A[0][1] = C[0][2] * C[2][1] - C[0][1] * C[2][2];
+  A[0][2] = C[0][1] * C[1][2] - C[0][2] * C[1][1];
+  A[1][1] = C[0][0] * C[2][2] - C[0][2] * C[2][0];
+  A[1][2] = C[0][2] * C[1][0] - C[0][0] * C[1][2];
+  A[2][2] = C[0][0] * C[1][1] - C[0][1] * C[1][0];
+  A[1][0] = A[0][1];
+  A[2][0] = A[0][2];
+  A[2][1] = A[1][2];
+  double x[3] = {0.0, 0.0, 0.0};
+  bool ok = false;
+  for (int it = 0; it < 13; ++it) {
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m = fmax(m, fabs(A[i / 3][i % 3]));
+    if (!(m > 0.0) || !(m <= 1.7976931348623157e308)) break;
+    const double r = 1.0 / m;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[i / 3][i % 3] *= r;
+    // column of largest norm, scaled to max |component| = 1
+    int k = 0;
+    double best = -1.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double s = A[0][j] * A[0][j] + A[1][j] * A[1][j] + A[2][j] * A[2][j];
+      if (s > best) {
+        best = s;
+        k = j;
+      }
+    }
+    double y[3] = {A[0][k], A[1][k], A[2][k]};
+    const double my = fmax(fabs(y[0]), fmax(fabs(y[1]), fabs(y[2])));
+    // orient like the previous estimate, then compare directions
+    double dot = y[0] * x[0] + y[1] * x[1] + y[2] * x[2];
+    const double sg = dot < 0.0 ? -1.0 / my : 1.0 / my;
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      y[i] *= sg;
+      d = fmax(d, fabs(y[i] - x[i]));
+      x[i] = y[i];
+    }
+    if (it > 0 && d <= 1e-14) {
+      ok = true;
+      break;
+    }
+    double S[3][3];
+    matmul3(A, A, S);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[i / 3][i % 3] = S[i / 3][i % 3];
+  }
+  if (!ok) {
+    double Cj[3][3];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Cj[i / 3][i % 3] = C[i / 3][i % 3];
+    smallest_eigvec3(Cj, v);
+    return;
+  }
+  const double r = 1.0 / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = x[i] * r;
+}
+
 // The per-pair solve from the centred moments m (layout of refit_kernel's
 // pass 2), the count n and the centroids: H (row-major, double) = T2^-1 Hn T1,
 // or zeros when X^T X is singular.
@@ -173,7 +275,7 @@ __host__ __device__ inline void refit_solve(const double *m, double n, double cx
 #pragma unroll
       for (int j = i + 1; j < 3; ++j) C[i][j] = C[j][i] = 0.5 * (C[i][j] + C[j][i]);
     double h3[3];
-    smallest_eigvec3(C, h3);
+    smallest_eigvec3_adj(C, h3);
     double Hn[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -208,13 +310,18 @@ __global__ __launch_bounds__(kRefitThreads) void refit_kernel(
   __shared__ double cen[5];
   // pass 1: count and centroids
   double s1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = a + threadIdx.x; i < b; i += kRefitThreads) {
-    if (mask && !mask[i]) continue;
-    s1[0] += 1.0;
-    s1[1] += static_cast<double>(X1[i]);
-    s1[2] += static_cast<double>(Y1[i]);
-    s1[3] += static_cast<double>(X2[i]);
-    s1[4] += static_cast<double>(Y2[i]);
+  for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
+    PointBatch pb;
+    load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (!pb.sel[j]) continue;
+      s1[0] += 1.0;
+      s1[1] += static_cast<double>(pb.x1[j]);
+      s1[2] += static_cast<double>(pb.y1[j]);
+      s1[3] += static_cast<double>(pb.x2[j]);
+      s1[4] += static_cast<double>(pb.y2[j]);
+    }
   }
   refit_block_sum(s1);
   if (threadIdx.x == 0) {
@@ -241,20 +348,25 @@ __global__ __launch_bounds__(kRefitThreads) void refit_kernel(
   double m[kMoments];
 #pragma unroll
   for (int k = 0; k < kMoments; ++k) m[k] = 0.0;
-  for (int64_t i = a + threadIdx.x; i < b; i += kRefitThreads) {
-    if (mask && !mask[i]) continue;
-    const double x = static_cast<double>(X1[i]) - cx, y = static_cast<double>(Y1[i]) - cy;
-    const double u = static_cast<double>(X2[i]) - cu, v = static_cast<double>(Y2[i]) - cv;
-    const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
-    const double uu = u * u, vv = v * v;
+  for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
+    PointBatch pb;
+    load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) m[k] += mono[k];
+    for (int j = 0; j < kBatch; ++j) {
+      if (!pb.sel[j]) continue;
+      const double x = static_cast<double>(pb.x1[j]) - cx, y = static_cast<double>(pb.y1[j]) - cy;
+      const double u = static_cast<double>(pb.x2[j]) - cu, v = static_cast<double>(pb.y2[j]) - cv;
+      const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
+      const double uu = u * u, vv = v * v;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      m[5 + k] += u * mono[k];
-      m[11 + k] += uu * mono[k];
-      m[17 + k] += v * mono[k];
-      m[23 + k] += vv * mono[k];
+      for (int k = 0; k < 5; ++k) m[k] += mono[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        m[5 + k] += u * mono[k];
+        m[11 + k] += uu * mono[k];
+        m[17 + k] += v * mono[k];
+        m[23 + k] += vv * mono[k];
+      }
     }
   }
   refit_block_sum(m);

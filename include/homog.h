@@ -184,7 +184,8 @@ int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t
  * log(1 - eps^4)), or when m reaches n_hyp_max (the cap). The result is the
  * best hypothesis among the m evaluated; n_evaluated[p] = m. Rounds of all
  * pairs run in one persistent launch, round-major; rounds started before a
- * pair's stopping point was known are discarded, so results do not depend on
+ * pair's stopping point was known are abandoned once a wave sees it (checked
+ * every 8 hypotheses) and are never merged, so results do not depend on
  * timing. Same arguments as hg_ransac_batched otherwise (no per-hypothesis
  * counts); 0 < confidence < 1; tune->hyps_per_block is ignored (64).
  * ws >= hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max) bytes.               */

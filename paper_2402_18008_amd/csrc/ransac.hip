@@ -105,11 +105,17 @@ __device__ __forceinline__ float bcast(float v) {
 // among the points [base, base + n) held in registers (P per lane); each wave
 // adds its counts into cnt[h] (LDS atomics). TAIL: the chunk runs past n and
 // lanes beyond it are masked out of the ballots.
+// Under adaptive termination `stop` points at the pair's stopping round and
+// `hb` is this item's round: every 8 hypotheses the wave re-reads it and gives
+// up a round that is no longer needed (returns false). The stopping round only
+// ever decreases and rounds at or past it are never merged, so an abandoned
+// round changes no result.
 template <int P, bool TAIL>
-__device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
+__device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
                                             const float *X2, const float *Y2, uint32_t c0,
                                             uint32_t n, const float (*Hs)[9], uint64_t vmask,
-                                            int nh, uint32_t *cnt) {
+                                            int nh, uint32_t *cnt, const uint32_t *stop,
+                                            uint32_t hb) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   float x1[P], y1[P], x2[P], y2[P];
@@ -125,6 +131,9 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
     if (TAIL) live[p] = __ballot(i < n);
   }
   for (int h = 0; h < nh; ++h) {
+    if (stop && (h & 7) == 7 &&
+        hb >= __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
     if (!((vmask >> h) & 1ull)) continue;
     float hh[9];
 #pragma unroll
@@ -138,6 +147,7 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
     }
     if (lane == 0 && c) atomicAdd(&cnt[h], c);
   }
+  return true;
 }
 
 // Full chunks of P points per lane, then (P = 16) chunks of 8, then one
@@ -147,23 +157,24 @@ __device__ __forceinline__ void score_chunk(const RansacArgs &a, const float *X1
 template <int P>
 __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
                                            const float (*Hs)[9], uint64_t vmask, int nh,
-                                           uint32_t *cnt) {
+                                           uint32_t *cnt, const uint32_t *stop = nullptr,
+                                           uint32_t hb = 0u) {
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   constexpr uint32_t kChunk = kWaves * 64 * P;
   constexpr uint32_t kChunk8 = kWaves * 64 * 8, kChunk4 = kWaves * 64 * 4;
   uint32_t c0 = 0;
   for (; c0 + kChunk <= n; c0 += kChunk)
-    score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+    if (!score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
   if (P > 8) {
     for (; c0 + kChunk8 <= n; c0 += kChunk8)
-      score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+      if (!score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
   }
   if (c0 < n) {
     if (n - c0 <= kChunk4)
-      score_chunk<4, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+      score_chunk<4, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
     else
-      score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt);
+      score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
   }
 }
 
@@ -326,8 +337,20 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   // 2. score (validity as a wave-uniform bit mask)
   const int lane = threadIdx.x & 63;
   const uint64_t vmask = __ballot(lane < nh && sm.valid[lane] != 0u);
-  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt);
+  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt, adaptive ? &a.pst[p].stop : nullptr,
+                static_cast<uint32_t>(hb));
   __syncthreads();
+  if (adaptive) {
+    // a wave may have given the round up: then it is at or past the stopping
+    // round (which only decreases), and nothing of it is published
+    if (threadIdx.x == 0)
+      sm.skip = static_cast<uint32_t>(hb) >=
+                __hip_atomic_load(&a.pst[p].stop, __ATOMIC_RELAXED, HG_AGENT);
+    __syncthreads();
+    const bool skip = sm.skip != 0u;
+    __syncthreads();
+    if (skip) return;
+  }
   // 3. publish counts and the block's best key (wave 0 holds all HB <= 64)
   if (threadIdx.x < 64) {
     const int t = threadIdx.x;

@@ -163,6 +163,31 @@ def bench_affine(stream, S, D, steps=20, warmup=3):
                         "frac_hbm": AFFINE_BYTES * n / (k * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def cpu_oracle_extras():
+    """The oracle on the other workloads, timed on the host (bounded samples):
+    single-pair RANSAC scoring (float64 NumPy, one process) and the
+    differentiable pipeline (torch float64 autograd through the DLT solve)."""
+    import torch
+    import synth
+    from oracle import ransac as oref
+    from oracle import warp as ow
+    cs = synth.config2()
+    t = time.perf_counter()
+    oref.ransac_ref(cs.corr, 4096, 3.0, 2)
+    dt_r = time.perf_counter() - t
+    pb = synth.patches(64, 4)
+    t = time.perf_counter()
+    ow.loss_and_grad(pb.offsets, pb.img, pb.tgt)
+    dt_w = time.perf_counter() - t
+    return {"ransac_2000x4096": {"hyp_pts_per_s": 2000 * 4096 / dt_r, "seconds": dt_r, "cores": 1,
+                                 "sample": "oracle RANSAC (Philox + Floyd, float64 ACA, float64 "
+                                           "transfer-error test) on the full single-pair workload"},
+            "warp_l1_128x128": {"patches_per_s": 64 / dt_w, "seconds": dt_w,
+                                "cores": torch.get_num_threads(),
+                                "sample": "float64 autograd through the DLT solve, bilinear warp "
+                                          "and L1, forward + backward, 64 patches of 128 x 128"}}
+
+
 FP32_FLOP_PER_HYP_PT = 21   # the division-free test as 21 FLOP (FMA = 2): 3 rows x 2 FMA,
                             # 2 FMA residuals, mul + FMA norm, (tau w)^2; the kernel folds
                             # tau into the operands and issues 12 VALU instructions
@@ -482,6 +507,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(src, dst, n, workers)
+        if args.part == "all":
+            extra["cpu_oracle"] = cpu_oracle_extras()
     print(json.dumps(out), flush=True)
 
 

@@ -491,6 +491,17 @@ def main():
         t, p = time_launches(lambda: hgpu.hg_stream_copy(S, C), 10, 2, stream)
         extra["stream_copy_same_pattern_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
         del C
+        # batch-size sweep (the sizes of the paper's GPU table, then larger): time per launch
+        # of a prefix of the same planes (plane stride stays 2^26)
+        sweep = {}
+        for m in (1, 10, 100, 1000, 10000, 100000, 1000000, 10000000, n):
+            sm_, dm_, hm_, fm_ = S[:, :m], D[:, :m], H[:, :m], F[:m]
+            reps = 200 if m <= 100000 else 30
+            t, p = time_launches(lambda: hgpu.hg_solve4(sm_, dm_, hgpu.HG_ACA, H=hm_, flags=fm_),
+                                 reps, 10, stream)
+            us = float(np.median(p)) * 1e3
+            sweep[str(m)] = {"us_per_launch": us, "homographies_per_s": m / (us * 1e-6)}
+        extra["aca_batch_size_sweep"] = sweep
         # small batch latency: 4096 quadruples
         for meth, name in ((hgpu.HG_ACA, "aca"), (hgpu.HG_SKS, "sks")):
             s4, d4 = S[:, :4096], D[:, :4096]

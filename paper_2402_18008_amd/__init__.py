@@ -174,6 +174,31 @@ def hg_ransac_batched_ws_bytes(n_pairs, n_hyp):
     return int(_abi.lib().hg_ransac_batched_ws_bytes(int(n_pairs), int(n_hyp)))
 
 
+def _check_off(off, total, min_pts, name="off"):
+    """Host-side check of pair offsets (one device-to-host copy): contiguous
+    int64, non-decreasing, off[0] >= 0, off[-1] <= total, and every pair with
+    at least ``min_pts`` points."""
+    _c(off, name, torch.int64)
+    if off.dim() != 1 or off.numel() < 1:
+        raise ValueError(f"{name} must be a 1-D tensor of n_pairs + 1 offsets")
+    o = off.cpu()
+    if int(o[0]) < 0 or int(o[-1]) > total:
+        raise ValueError(f"{name} must lie in [0, {total}]")
+    if off.numel() > 1:
+        d = o[1:] - o[:-1]
+        if bool((d < min_pts).any()):
+            raise ValueError(f"{name} must be non-decreasing with pairs of >= {min_pts} points")
+
+
+def _out(t, name, dtype, numel, device):
+    if t is None:
+        return None
+    _c(t, name, dtype)
+    if t.numel() < numel or t.device != device:
+        raise ValueError(f"{name} must hold {numel} elements on {device}")
+    return t
+
+
 def _tuning(tune):
     if tune is None:
         return None
@@ -188,13 +213,16 @@ def hg_refit_ho(corr, off, mask=None, H=None, n_used=None, flags=None, stream=No
     the device, mask (total,) uint8 or None (all points). Returns (H
     (n_pairs, 9) float32, n_used (n_pairs,) int32, flags (n_pairs,) uint8)."""
     ld, total = _corr_planes(corr)
-    _dev(off, "off", torch.int64)
+    _check_off(off, total, 0)
     n_pairs = off.numel() - 1
     dev = corr.device
     if mask is not None:
-        _dev(mask, "mask", torch.uint8)
+        _c(mask, "mask", torch.uint8)
         if mask.numel() < total:
             raise ValueError("mask must cover every point")
+    H = _out(H, "H", torch.float32, 9 * n_pairs, dev)
+    n_used = _out(n_used, "n_used", torch.int32, n_pairs, dev)
+    flags = _out(flags, "flags", torch.uint8, n_pairs, dev)
     H = torch.empty((n_pairs, 9), dtype=torch.float32, device=dev) if H is None else H
     n_used = torch.empty(n_pairs, dtype=torch.int32, device=dev) if n_used is None else n_used
     flags = torch.empty(n_pairs, dtype=torch.uint8, device=dev) if flags is None else flags
@@ -214,7 +242,7 @@ class BatchedRansac:
 
     def __init__(self, corr, off, n_hyp, thresh, seed, hyp_counts=False):
         self.ld, self.total = _corr_planes(corr)
-        _dev(off, "off", torch.int64)
+        _check_off(off, self.total, 4)
         self.corr, self.off = corr, off
         self.n_pairs = off.numel() - 1
         self.n_hyp, self.thresh, self.seed = int(n_hyp), float(thresh), int(seed) & (2**64 - 1)
@@ -264,7 +292,7 @@ class AdaptiveRansac:
 
     def __init__(self, corr, off, n_hyp_max, thresh, seed, confidence=0.99):
         self.ld, self.total = _corr_planes(corr)
-        _dev(off, "off", torch.int64)
+        _check_off(off, self.total, 4)
         self.corr, self.off = corr, off
         self.n_pairs = off.numel() - 1
         self.n_hyp, self.thresh = int(n_hyp_max), float(thresh)

@@ -77,10 +77,11 @@ struct PairState {
 
 __device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &base, uint32_t &n) {
   if (a.off) {
-    base = a.off[p];
-    const int64_t e = a.off[p + 1];
+    // clamped into the planes, so that offsets outside them cannot move an access out
+    base = min(max(a.off[p], int64_t(0)), a.ld);
+    const int64_t e = min(max(a.off[p + 1], base), a.ld);
     const int64_t m = e - base;
-    n = (m < 0) ? 0u : (m > 0x7FFFFFFF ? 0x7FFFFFFFu : static_cast<uint32_t>(m));
+    n = m > 0x7FFFFFFF ? 0x7FFFFFFFu : static_cast<uint32_t>(m);
   } else {
     base = 0;
     n = static_cast<uint32_t>(a.n_single);

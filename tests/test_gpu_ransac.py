@@ -311,3 +311,20 @@ def test_adaptive_extremes():
         got = dict(best_H=ar.best_H[p].cpu().numpy(), best_count=int(ar.best_count[p]),
                    best_hyp=int(ar.best_hyp[p]), n_eval=int(ne[p]), mask=ar.mask[a:b].cpu().numpy())
         check_adaptive_pair(corr[:, a:b], 700, 3, p, got, f"extreme {p}")
+
+
+def test_batched_rejects_bad_offsets():
+    """Offsets are checked on the host before any launch: decreasing, out of
+    range, or a pair with fewer than 4 points is refused."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    corr = torch.zeros((4, 100), device="cuda")
+    for bad in ([0, 50, 40, 100], [0, 50, 101], [-1, 50, 100], [0, 3, 100]):
+        off = torch.tensor(bad, dtype=torch.int64, device="cuda")
+        with pytest.raises(ValueError):
+            hgpu.BatchedRansac(corr, off, 64, TAU, 1)
+        with pytest.raises(ValueError):
+            hgpu.AdaptiveRansac(corr, off, 64, TAU, 1)
+    off = torch.tensor([0, 50, 100], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        hgpu.hg_refit_ho(corr, off, H=torch.empty(9, device="cuda"))

@@ -901,11 +901,27 @@ extern "C" int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *
                              ws_bytes))
     return st;
   const hipStream_t s = as_stream(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // frees whatever was obtained, on every return path
+  struct Scratch {
+    float **bh;
+    int32_t **bc, **bi;
+    uint8_t **mk;
+    hipEvent_t *e0, *e1;
+    ~Scratch() {
+      if (*e0) (void)hipEventDestroy(*e0);
+      if (*e1) (void)hipEventDestroy(*e1);
+      if (*bh) (void)hipFree(*bh);
+      if (*bc) (void)hipFree(*bc);
+      if (*bi) (void)hipFree(*bi);
+      if (*mk) (void)hipFree(*mk);
+    }
+  } scratch{&bh, &bc, &bi, &mk, &e0, &e1};
   HG_HIP(hipMalloc(&bh, 36ull * n_pairs));
   HG_HIP(hipMalloc(&bc, 4ull * n_pairs));
   HG_HIP(hipMalloc(&bi, 4ull * n_pairs));
-  HG_HIP(hipMalloc(&mk, static_cast<size_t>(std::max<int64_t>(total, 1))));
-  hipEvent_t e0, e1;
+  // the kernels clamp pair ranges into [0, ld), so a mask of ld bytes covers any offsets
+  HG_HIP(hipMalloc(&mk, static_cast<size_t>(std::max<int64_t>(ld, 1))));
   HG_HIP(hipEventCreate(&e0));
   HG_HIP(hipEventCreate(&e1));
   float best_ms = 1e30f;
@@ -936,13 +952,7 @@ extern "C" int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *
         }
       }
 done:
-  (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(bh);
-  (void)hipFree(bc);
-  (void)hipFree(bi);
-  (void)hipFree(mk);
+  (void)hipStreamSynchronize(s);   // the scratch buffers are released when this returns
   if (status != HG_OK) return status;
   *out = best;
   {

@@ -60,6 +60,54 @@ def measured_traffic(n):
     return t.get("bytes_per_launch")
 
 
+def write_traffic(fetch_dir, write_dir, n):
+    """Solver HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters
+    (KiB per dispatch), each scaled by what the same counter reads for a plain
+    copy of known size in the same run; written to TRAFFIC_FILE."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(folder, counter):
+        per = defaultdict(list)
+        with open(os.path.join(folder, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: 1024.0 * sum(v) / len(v) for k, v in per.items()}
+
+    def pick(d, key):
+        ks = [k for k in d if key in k]
+        if len(ks) != 1:
+            raise SystemExit(f"expected one kernel matching {key!r}, found {ks}")
+        return d[ks[0]]
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = 8 * n * 4                      # the 8 source planes, each way
+    f_copy, w_copy = pick(fetch, "stream_copy4_kernel"), pick(write, "stream_copy4_kernel")
+    f_sol, w_sol = pick(fetch, "solve4_kernel<0>"), pick(write, "solve4_kernel<0>")
+    ff, wf = copy_bytes / f_copy, copy_bytes / w_copy
+    cmd = ("rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c} -o run -- python3 "
+           "bench.py --part solver --with-copy --steps 3 --warmup 1 --no-cpu-baseline "
+           "--gen-workers 1")
+    out = {
+        "kernel": "solve4_kernel<ACA>", "n": n, "source_hash": solver_hash(),
+        "command_fetch": cmd.format(c="FETCH_SIZE"), "command_write": cmd.format(c="WRITE_SIZE"),
+        "command_summary": "python3 bench.py --traffic-from gpurun_out/pmc_FETCH_SIZE "
+                           "gpurun_out/pmc_WRITE_SIZE",
+        "fetch_kib_per_dispatch": f_sol / 1024, "write_kib_per_dispatch": w_sol / 1024,
+        "copy_fetch_kib_per_dispatch": f_copy / 1024, "copy_write_kib_per_dispatch": w_copy / 1024,
+        "copy_bytes_each_way": copy_bytes, "fetch_factor": ff, "write_factor": wf,
+        "fetch_bytes": f_sol * ff, "write_bytes": w_sol * wf,
+        "bytes_per_launch": f_sol * ff + w_sol * wf,
+        "algorithmic_bytes_per_launch": BYTES_PER_QUAD * n,
+    }
+    out["traffic_over_algorithmic"] = out["bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def time_launches(fn, steps, warmup, stream):
     """Run fn() warmup times, then time `steps` calls with one event pair each.
     Returns (total_ms, per_launch_ms list)."""
@@ -124,6 +172,34 @@ def cpu_baseline(src, dst, n_sample, workers):
 
 SK_BYTES = 32 + 36 + 1            # 8 fp32 in, 9 fp32 out, 1 flag byte
 AFFINE_BYTES = 48 + 24 + 1        # 12 fp32 in, 6 fp32 out, 1 flag byte
+
+
+def stream_ceilings(stream, S, D, H, F, solver_GBps):
+    """Streaming rates with no arithmetic: a plain copy, and each solver's exact
+    read/write mix and launch shape (16 -> 9 planes + flags for hg_solve4,
+    8 -> 9 for the simplified SK, 12 -> 6 for the affine map)."""
+    import numpy as np
+    import torch
+    import paper_2402_18008_amd as hgpu
+    n = S.shape[1]
+    out = {}
+    C = torch.empty_like(S)
+    t, p = time_launches(lambda: hgpu.hg_stream_copy(S, C), 20, 3, stream)
+    out["copy_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
+    del C
+    X = torch.empty((16, n), dtype=torch.float32, device=S.device)
+    X[:8].copy_(S)
+    X[8:].copy_(D)
+    for name, n_in, n_out in (("solve4_16to9", 16, 9), ("sk_8to9", 8, 9),
+                              ("affine_12to6", 12, 6)):
+        xi, ho = X[:n_in], H[:n_out]
+        t, p = time_launches(lambda: hgpu.hg_stream_planes(xi, n_out, out=ho, flags=F), 20, 3,
+                             stream)
+        out[f"{name}_GBps"] = (4 * (n_in + n_out) + 1) * n / (np.mean(p) * 1e-3) / 1e9
+    del X
+    torch.cuda.synchronize()
+    out["solve4_frac_of_its_mix"] = solver_GBps / out["solve4_16to9_GBps"]
+    return out
 
 
 def bench_sk(stream, n, workers, steps=20, warmup=3):
@@ -391,15 +467,22 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="with --part solver: also run a plain 4 GiB device copy (reference "
                          "for hardware byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU run: write the solver's measured HBM traffic per launch from "
+                         "two rocprofv3 --pmc output folders (FETCH_SIZE, then WRITE_SIZE) of "
+                         "'--part solver --with-copy' runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="host processes for input generation (fewer under a profiler)")
     args = ap.parse_args()
     if args.solver_only:
         args.part = "solver"
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, args.n)
+        return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the hot path "
-              f"has no multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): every kernel "
+              f"of the hot path runs on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -485,12 +568,7 @@ def main():
         t, p = time_launches(sks, 20, 3, stream)
         extra["sks_2p26"] = {"homographies_per_s": n / (t / 20 * 1e-3),
                              "GBps": BYTES_PER_QUAD * n / (np.mean(p) * 1e-3) / 1e9}
-        # plain copy of the input planes with the solver's access pattern (one float
-        # per lane), for reference
-        C = torch.empty_like(S)
-        t, p = time_launches(lambda: hgpu.hg_stream_copy(S, C), 10, 2, stream)
-        extra["stream_copy_same_pattern_GBps"] = 2 * S.numel() * 4 / (np.mean(p) * 1e-3) / 1e9
-        del C
+        extra["stream_ceilings"] = stream_ceilings(stream, S, D, H, F, achieved)
         # batch-size sweep (the sizes of the paper's GPU table, then larger): time per launch
         # of a prefix of the same planes (plane stride stays 2^26)
         sweep = {}

@@ -113,12 +113,25 @@ int hg_solve_sk(const double *obj, const float *dst, int64_t n, int64_t ld, floa
 int hg_solve3_affine(const float *src, const float *dst, int64_t n, int64_t ld, float *A,
                      uint8_t *flags, void *stream);
 
-/* Plain device copy of n floats with the access pattern of hg_solve4 (one
- * float per lane, 512-thread workgroups, non-temporal loads and stores). Not
- * part of the method: it is the reference for calibrating hardware byte
- * counters and the streaming ceiling of that pattern. n == 0 is a no-op;
- * NULL pointer or n < 0 -> HG_EINVAL.                                       */
+/* Plain device copy of n floats (16 bytes per lane when both pointers are
+ * 16-byte aligned, one float per lane for the rest; 512-thread workgroups,
+ * non-temporal loads and stores). Not part of the method: it is the reference
+ * for calibrating hardware byte counters and the plain-copy streaming rate.
+ * n == 0 is a no-op; NULL pointer or n < 0 -> HG_EINVAL.                    */
 int hg_stream_copy(const float *src, float *dst, int64_t n, void *stream);
+
+/* Streaming ceiling of a solver's access pattern. Not part of the method: it
+ * moves the bytes of one solver kernel without its arithmetic, with the same
+ * launch shape (one element per lane, 512-thread workgroups, a grid covering
+ * the batch once, non-temporal loads and stores). in: n_in float planes of n
+ * elements, plane stride ld; out: n_out float planes, stride ld, where out
+ * plane j = in[j mod n_in] + in[j + n_out] (second term only if
+ * j + n_out < n_in); flags (optional, n bytes) = (in plane 0 < 0). Supported
+ * shapes: 16 -> 9 (hg_solve4), 8 -> 9 (hg_solve_sk), 12 -> 6
+ * (hg_solve3_affine). n == 0 is a no-op; other shapes, NULL in/out or
+ * ld < n -> HG_EINVAL.                                                      */
+int hg_stream_planes(const float *in, int32_t n_in, float *out, int32_t n_out, uint8_t *flags,
+                     int64_t n, int64_t ld, void *stream);
 
 /* ---- single-pair RANSAC --------------------------------------------------
  * Hypothesise and verify (RANSAC stage of the experiments): hypothesis j

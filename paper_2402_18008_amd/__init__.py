@@ -107,8 +107,8 @@ def hg_solve3_affine(src, dst, A=None, flags=None, stream=None):
 
 
 def hg_stream_copy(src, dst=None, stream=None):
-    """Copy a float32 tensor with the solver's access pattern (reference for
-    byte counters and streaming ceilings)."""
+    """Plain copy of a float32 tensor (reference for byte counters and the
+    plain-copy streaming rate; not part of the method)."""
     _dev(src, "src")
     if not src.is_contiguous():
         raise ValueError("src must be contiguous")
@@ -116,6 +116,30 @@ def hg_stream_copy(src, dst=None, stream=None):
         dst = torch.empty_like(src)
     _abi.call("hg_stream_copy", src.data_ptr(), dst.data_ptr(), src.numel(), _stream(stream))
     return dst
+
+
+def hg_stream_planes(inp, n_out, out=None, flags=None, stream=None):
+    """Move a solver's bytes without its arithmetic: (n_in, n) float32 planes
+    in, (n_out, n) planes and n flag bytes out, with the solver kernels'
+    launch shape (the streaming ceiling of that read/write mix; not part of the
+    method). Shapes 16 -> 9, 8 -> 9 and 12 -> 6."""
+    _dev(inp, "inp")
+    if inp.dim() != 2 or inp.stride(1) != 1:
+        raise ValueError("inp must be (n_in, n) with unit stride along n")
+    n_in, n = inp.shape
+    ld = inp.stride(0)
+    if out is None:
+        out = torch.empty((n_out, ld), dtype=torch.float32, device=inp.device)[:, :n]
+    if out.shape != (n_out, n) or out.stride() != (ld, 1):
+        raise ValueError("out must be (n_out, n) with the plane stride of inp")
+    _dev(out, "out")
+    if flags is not None:
+        _dev(flags, "flags", torch.uint8)
+        if flags.numel() < n or not flags.is_contiguous():
+            raise ValueError("flags must be contiguous with n elements")
+    _abi.call("hg_stream_planes", inp.data_ptr(), n_in, out.data_ptr(), n_out,
+              None if flags is None else flags.data_ptr(), n, ld, _stream(stream))
+    return out
 
 
 # ---- RANSAC ----------------------------------------------------------------

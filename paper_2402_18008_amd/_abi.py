@@ -35,6 +35,7 @@ SIGNATURES = {
     "hg_version": (C.c_int, []),
     "hg_solve4": (C.c_int, [C.c_int, vp, vp, i64, i64, vp, vp, vp]),
     "hg_stream_copy": (C.c_int, [vp, vp, i64, vp]),
+    "hg_stream_planes": (C.c_int, [vp, i32, vp, i32, vp, i64, i64, vp]),
     "hg_solve_sk": (C.c_int, [C.POINTER(C.c_double), vp, i64, i64, vp, vp,
                               C.POINTER(C.c_double), vp]),
     "hg_solve3_affine": (C.c_int, [vp, vp, i64, i64, vp, vp, vp]),

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhomog.so")
 
-SOURCES = ["status.hip", "solve.hip", "ransac.hip", "diff.hip", "refit.hip"]
+SOURCES = ["status.hip", "solve.hip", "ransac.hip", "diff.hip", "refit.hip", "stream.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

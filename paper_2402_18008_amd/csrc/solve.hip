@@ -123,31 +123,7 @@ static SkPattern sk_pattern(const double *o, double *frame) {
   return p;
 }
 
-// Plain copy with the solver's access pattern (one float per lane, 512-thread
-// workgroups, non-temporal): the reference for calibrating hardware byte
-// counters and the streaming ceiling of that pattern.
-__global__ __launch_bounds__(kSolveThreads) void stream_copy_kernel(const float *__restrict__ src,
-                                                                    float *__restrict__ dst,
-                                                                    int64_t n) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += stride)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
-}
-
 }  // namespace hg
-
-extern "C" int hg_stream_copy(const float *src, float *dst, int64_t n, void *stream) {
-  hg::clear_error();
-  HG_REQUIRE(n >= 0, "hg_stream_copy: n < 0");
-  if (n == 0) return HG_OK;
-  HG_REQUIRE(src && dst, "hg_stream_copy: NULL pointer");
-  const int64_t blocks = (n + hg::kSolveThreads - 1) / hg::kSolveThreads;
-  const unsigned grid = static_cast<unsigned>(blocks > 0x7FFFFFFF ? 0x7FFFFFFF : blocks);
-  hipLaunchKernelGGL(hg::stream_copy_kernel, dim3(grid), dim3(hg::kSolveThreads), 0,
-                     hg::as_stream(stream), src, dst, n);
-  return hg::launched("stream_copy_kernel");
-}
 
 extern "C" int hg_solve4(int method, const float *src, const float *dst, int64_t n, int64_t ld,
                          float *H, uint8_t *flags, void *stream) {

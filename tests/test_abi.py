@@ -213,6 +213,16 @@ def test_stream_copy_validation(lib):
     assert lib.hg_stream_copy(None, None, 0, None) == _abi.HG_OK
 
 
+def test_stream_planes_validation(lib):
+    assert lib.hg_stream_planes(FAKE, 16, FAKE, 9, None, -1, 10, None) == _abi.HG_EINVAL
+    assert lib.hg_stream_planes(None, 16, None, 9, None, 0, 0, None) == _abi.HG_OK
+    assert lib.hg_stream_planes(None, 16, FAKE, 9, None, 5, 5, None) == _abi.HG_EINVAL
+    assert lib.hg_stream_planes(FAKE, 16, FAKE, 9, None, 5, 4, None) == _abi.HG_EINVAL
+    for n_in, n_out in ((1, 1), (16, 8), (9, 9), (0, 9)):
+        assert lib.hg_stream_planes(FAKE, n_in, FAKE, n_out, None, 5, 5, None) == _abi.HG_EINVAL
+        assert b"unsupported shape" in lib.hg_last_error()
+
+
 def test_adaptive_validation(lib):
     need = lib.hg_ransac_adaptive_ws_bytes(512, 1000)
     assert need > lib.hg_ransac_batched_ws_bytes(512, 1000)

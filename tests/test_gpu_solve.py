@@ -127,9 +127,30 @@ def test_config1_full_size_sampled():
 def test_stream_copy():
     require_gpu()
     import paper_2402_18008_amd as hgpu
-    for n in (1, 513, 100003):
-        x = torch.randn(n, device="cuda")
+    for n in (1, 3, 4, 513, 100003):
+        x = torch.randn(n + 1, device="cuda")
         announce(f"stream copy n={n}")
-        y = hgpu.hg_stream_copy(x)
+        y = hgpu.hg_stream_copy(x[:n])                 # 16-byte path and tail
         torch.cuda.synchronize()
-        assert torch.equal(x, y)
+        assert torch.equal(x[:n], y)
+        y = torch.zeros(n + 1, device="cuda")
+        hgpu.hg_stream_copy(x[1:], y[1:])              # unaligned: one float per lane
+        torch.cuda.synchronize()
+        assert torch.equal(x[1:], y[1:]) and y[0] == 0
+
+
+@pytest.mark.parametrize("n_in,n_out", [(16, 9), (8, 9), (12, 6)])
+def test_stream_planes(n_in, n_out):
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    n, ld = 70001, 70400
+    X = torch.randn(n_in, ld, device="cuda")[:, :n]
+    F = torch.full((n + 1,), 7, dtype=torch.uint8, device="cuda")
+    announce(f"stream planes {n_in} -> {n_out} n={n}")
+    out = hgpu.hg_stream_planes(X, n_out, flags=F)
+    torch.cuda.synchronize()
+    x = X.cpu()
+    for j in range(n_out):
+        ref = x[j % n_in] + x[j + n_out] if j + n_out < n_in else x[j % n_in]
+        assert torch.equal(out[j].cpu(), ref), j
+    assert torch.equal(F[:n].cpu(), (x[0] < 0).to(torch.uint8)) and int(F[n]) == 7

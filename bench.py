@@ -239,14 +239,54 @@ def bench_affine(stream, S, D, steps=20, warmup=3):
                         "frac_hbm": AFFINE_BYTES * n / (k * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_oracle_extras():
     """The oracle on the other workloads, timed on the host (bounded samples):
-    single-pair RANSAC scoring (float64 NumPy, one process) and the
-    differentiable pipeline (torch float64 autograd through the DLT solve)."""
+    the host's CPU model and core count; ACA and SKS on one core (4096
+    quadruples and a 2^20 chunk); single-pair RANSAC scoring (float64 NumPy,
+    one process); the differentiable pipeline (torch float64 autograd through
+    the DLT solve)."""
     import torch
     import synth
     from oracle import ransac as oref
     from oracle import warp as ow
+    import numpy as np
+    from oracle import homography as hg
+    out = {"host": host_info()}
+    # the 4096-quadruple workload (seed 0) and a 2^20 chunk, each method on one core
+    for label, n_q in (("quads_4096", 4096), ("quads_2p20", 1 << 20)):
+        s, d, _ = synth.quadruples(n_q, 0)
+        s, d = s.astype(np.float64), d.astype(np.float64)
+        rates = {}
+        for name, fn in (("aca", hg.aca64), ("sks", hg.sks64)):
+            reps, t = 0, time.perf_counter()
+            while True:
+                fn(s, d)
+                reps += 1
+                dt = time.perf_counter() - t
+                if dt > 0.5:
+                    break
+            rates[f"{name}_homographies_per_s"] = reps * n_q / dt
+        out[label] = {**rates, "cores": 1,
+                      "sample": f"float64 NumPy oracle ACA and SKS over {n_q} quadruples, repeated "
+                                f"for at least 0.5 s, one process"}
     cs = synth.config2()
     t = time.perf_counter()
     oref.ransac_ref(cs.corr, 4096, 3.0, 2)
@@ -255,7 +295,8 @@ def cpu_oracle_extras():
     t = time.perf_counter()
     ow.loss_and_grad(pb.offsets, pb.img, pb.tgt)
     dt_w = time.perf_counter() - t
-    return {"ransac_2000x4096": {"hyp_pts_per_s": 2000 * 4096 / dt_r, "seconds": dt_r, "cores": 1,
+    return {**out,
+            "ransac_2000x4096": {"hyp_pts_per_s": 2000 * 4096 / dt_r, "seconds": dt_r, "cores": 1,
                                  "sample": "oracle RANSAC (Philox + Floyd, float64 ACA, float64 "
                                            "transfer-error test) on the full single-pair workload"},
             "warp_l1_128x128": {"patches_per_s": 64 / dt_w, "seconds": dt_w,

@@ -98,10 +98,6 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-__device__ __forceinline__ float bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
 // Count, for each hypothesis h < nh whose bit is set in vmask, the inliers
 // among the points [base, base + n) held in registers (P per lane); each wave
 // adds its counts into cnt[h] (LDS atomics). TAIL: the chunk runs past n and
@@ -136,9 +132,12 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
         hb >= __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return false;
     if (!((vmask >> h) & 1ull)) continue;
+    // H read from LDS by every lane (one address: a broadcast) and used from
+    // vector registers; scalar copies would cost a readfirstlane per entry and
+    // moves wherever an FMA needs two of them
     float hh[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) hh[k] = bcast(Hs[h][k]);
+    for (int k = 0; k < 9; ++k) hh[k] = Hs[h][k];
     uint32_t c = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -152,9 +151,9 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
 }
 
 // Full chunks of P points per lane, then (P = 16) chunks of 8, then one
-// masked tail chunk of 4 or 8 points per lane, so that a pair's last chunk
-// wastes at most a chunk of the smaller shape. Counts are integer sums over
-// the points, so the result does not depend on the chunking.
+// masked tail chunk of just enough 64-point rows per wave (1 to 8), so that a
+// pair's last chunk leaves fewer than 4 x 64 lane slots idle. Counts are
+// integer sums over the points, so the result does not depend on the chunking.
 template <int P>
 __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
                                            const float (*Hs)[9], uint64_t vmask, int nh,
@@ -163,7 +162,7 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   constexpr uint32_t kChunk = kWaves * 64 * P;
-  constexpr uint32_t kChunk8 = kWaves * 64 * 8, kChunk4 = kWaves * 64 * 4;
+  constexpr uint32_t kChunk8 = kWaves * 64 * 8;
   uint32_t c0 = 0;
   for (; c0 + kChunk <= n; c0 += kChunk)
     if (!score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
@@ -172,10 +171,24 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
       if (!score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
   }
   if (c0 < n) {
-    if (n - c0 <= kChunk4)
-      score_chunk<4, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
-    else
-      score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
+    // fewer than kChunk8 points remain: 1 .. 8 rows of 64 points per wave
+    const uint32_t rows = (n - c0 + 63u) / 64u;
+    switch ((rows + kWaves - 1) / kWaves) {
+#define HG_TAIL(R) \
+  case R:          \
+    score_chunk<R, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb); \
+    break;
+      HG_TAIL(1)
+      HG_TAIL(2)
+      HG_TAIL(3)
+      HG_TAIL(4)
+      HG_TAIL(5)
+      HG_TAIL(6)
+      HG_TAIL(7)
+      default:
+        score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
+#undef HG_TAIL
+    }
   }
 }
 

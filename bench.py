@@ -396,7 +396,8 @@ def bench_ransac_batched(stream):
     Hr = torch.empty((br.n_pairs, 9), dtype=torch.float32, device="cuda")
     ur = torch.empty(br.n_pairs, dtype=torch.int32, device="cuda")
     fr = torch.empty(br.n_pairs, dtype=torch.uint8, device="cuda")
-    t, p = time_launches(lambda: hgpu.hg_refit_ho(corr, off, br.mask, Hr, ur, fr), 20, 3, stream)
+    t, p = time_launches(lambda: hgpu.hg_refit_ho(corr, off, br.mask, Hr, ur, fr, off_host=cb.off),
+                         20, 3, stream)
     ms_refit = float(np.median(p))
     rate = hyp_pts / (ms_graph * 1e-3)
     return {"ransac_batched_512x1024": {

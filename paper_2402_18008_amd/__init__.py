@@ -198,14 +198,20 @@ def hg_ransac_batched_ws_bytes(n_pairs, n_hyp):
     return int(_abi.lib().hg_ransac_batched_ws_bytes(int(n_pairs), int(n_hyp)))
 
 
-def _check_off(off, total, min_pts, name="off"):
-    """Host-side check of pair offsets (one device-to-host copy): contiguous
-    int64, non-decreasing, off[0] >= 0, off[-1] <= total, and every pair with
-    at least ``min_pts`` points."""
+def _check_off(off, total, min_pts, name="off", off_host=None):
+    """Host-side check of pair offsets: contiguous int64, non-decreasing,
+    off[0] >= 0, off[-1] <= total, and every pair with at least ``min_pts``
+    points. Checks ``off_host`` (the caller's host copy of off) if given,
+    else copies off to the host (which waits for the stream)."""
     _c(off, name, torch.int64)
     if off.dim() != 1 or off.numel() < 1:
         raise ValueError(f"{name} must be a 1-D tensor of n_pairs + 1 offsets")
-    o = off.cpu()
+    if off_host is None:
+        o = off.cpu()
+    else:
+        o = torch.as_tensor(off_host, dtype=torch.int64).reshape(-1)
+        if o.numel() != off.numel():
+            raise ValueError(f"{name}_host must have the {off.numel()} entries of {name}")
     if int(o[0]) < 0 or int(o[-1]) > total:
         raise ValueError(f"{name} must lie in [0, {total}]")
     if off.numel() > 1:
@@ -231,13 +237,16 @@ def _tuning(tune):
     return Tuning(*(int(v) for v in tune), *([0] * (4 - len(tune))))
 
 
-def hg_refit_ho(corr, off, mask=None, H=None, n_used=None, flags=None, stream=None):
+def hg_refit_ho(corr, off, mask=None, H=None, n_used=None, flags=None, stream=None,
+                off_host=None):
     """HO-SVD least-squares homography per pair over the masked points.
     corr (4, total) float32 planes x1 y1 x2 y2, off (n_pairs + 1,) int64 on
-    the device, mask (total,) uint8 or None (all points). Returns (H
-    (n_pairs, 9) float32, n_used (n_pairs,) int32, flags (n_pairs,) uint8)."""
+    the device, mask (total,) uint8 or None (all points); off_host: a host
+    copy of off for the checks (else off is copied back, which waits for the
+    stream). Returns (H (n_pairs, 9) float32, n_used (n_pairs,) int32, flags
+    (n_pairs,) uint8)."""
     ld, total = _corr_planes(corr)
-    _check_off(off, total, 0)
+    _check_off(off, total, 0, off_host=off_host)
     n_pairs = off.numel() - 1
     dev = corr.device
     if mask is not None:

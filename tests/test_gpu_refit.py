@@ -56,6 +56,21 @@ def test_refit_ground_truth_masks():
     Hg, ug, fg = gpu_refit(b.corr, b.off, mask)
     w = check(b.corr, b.off, mask, Hg, ug, fg, label="gt")
     print("refit worst herr", w)
+    # the same call checked against a host copy of the offsets
+    import paper_2402_18008_amd as hgpu
+    C = torch.from_numpy(np.ascontiguousarray(b.corr)).cuda()
+    O = torch.from_numpy(b.off).cuda()
+    M = torch.from_numpy(mask).cuda()
+    H2, u2, f2 = hgpu.hg_refit_ho(C, O, M, off_host=b.off)
+    torch.cuda.synchronize()
+    assert np.array_equal(H2.cpu().numpy().reshape(-1, 3, 3), Hg)
+    assert np.array_equal(u2.cpu().numpy(), ug) and np.array_equal(f2.cpu().numpy(), fg)
+    bad = b.off.copy()
+    bad[3], bad[4] = bad[4], bad[3]
+    with pytest.raises(ValueError):
+        hgpu.hg_refit_ho(C, O, M, off_host=bad)
+    with pytest.raises(ValueError):
+        hgpu.hg_refit_ho(C, O, M, off_host=b.off[:-1])
 
 
 def test_refit_masks_small_sets_and_no_mask():

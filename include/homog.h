@@ -196,10 +196,13 @@ int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t
  * evaluated, (1 - eps^4)^m <= 1 - confidence (i.e. m >= log(1 - confidence) /
  * log(1 - eps^4)), or when m reaches n_hyp_max (the cap). The result is the
  * best hypothesis among the m evaluated; n_evaluated[p] = m. Rounds of all
- * pairs run in one persistent launch, round-major; rounds started before a
- * pair's stopping point was known are abandoned once a wave sees it (checked
- * every 8 hypotheses) and are never merged, so results do not depend on
- * timing. Same arguments as hg_ransac_batched otherwise (no per-hypothesis
+ * pairs run in one persistent launch, queued by (2r + 1) / N_p (round r of a
+ * pair of N_p points; large pairs' rounds spread through the queue) when
+ * n_pairs^2 * rounds <= 2^27, else round-major. Rounds past a pair's stopping
+ * point (or past the bound that the best count so far gives) are skipped, or
+ * abandoned once a wave sees it (checked every 8 hypotheses), and are never
+ * merged, so results do not depend on order or timing. Same arguments as
+ * hg_ransac_batched otherwise (no per-hypothesis
  * counts); 0 < confidence < 1; tune->hyps_per_block is ignored (64).
  * ws >= hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max) bytes.               */
 size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max);

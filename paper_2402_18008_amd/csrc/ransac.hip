@@ -62,6 +62,7 @@ struct RansacArgs {
   struct PairState *pst;
   unsigned long long *rkey;
   uint32_t *rdone;
+  int32_t *iorder;         // adaptive: queue position -> pair * n_hb + round, or NULL
   int32_t *n_eval;
   double one_minus_conf;
 };
@@ -233,6 +234,7 @@ __device__ bool adaptive_advance(const RansacArgs &a, int p, uint32_t n_pts, int
     uint32_t s = __hip_atomic_load(&st->stop, __ATOMIC_RELAXED, HG_AGENT);
     unsigned long long best = __hip_atomic_load(&st->best, __ATOMIC_RELAXED, HG_AGENT);
     const uint32_t finished = __hip_atomic_load(&st->finished, __ATOMIC_RELAXED, HG_AGENT);
+    const uint32_t f0 = f;
     while (f < s && __hip_atomic_load(&rdone[f], __ATOMIC_SEQ_CST, HG_AGENT) != 0u) {
       const unsigned long long k = __hip_atomic_load(&rkey[f], __ATOMIC_RELAXED, HG_AGENT);
       best = k > best ? k : best;
@@ -242,6 +244,22 @@ __device__ bool adaptive_advance(const RansacArgs &a, int p, uint32_t n_pts, int
       if (m >= static_cast<uint32_t>(a.n_hyp) || enough_samples(bc, n_pts, m, a.one_minus_conf)) {
         s = f;
         __hip_atomic_store(&st->stop, s, __ATOMIC_RELAXED, HG_AGENT);
+      }
+    }
+    if (f > f0 && f < s) {
+      // The best count only grows and the rule is monotone in it (for a fixed
+      // number of hypotheses), so the rule will hold at the latest after the
+      // first round at which it holds with the current best: later rounds
+      // are never merged, and lowering `stop` to there lets the workgroups skip
+      // or abandon them. The merge above then ends on the rule, as before.
+      const uint32_t bc = best ? static_cast<uint32_t>((best >> 32) - 1ull) : 0u;
+      for (uint32_t c = f + 1u; c < s; ++c) {
+        const uint32_t m = min(c * static_cast<uint32_t>(HB), static_cast<uint32_t>(a.n_hyp));
+        if (enough_samples(bc, n_pts, m, a.one_minus_conf)) {
+          s = c;
+          __hip_atomic_store(&st->stop, s, __ATOMIC_RELAXED, HG_AGENT);
+          break;
+        }
       }
     }
     __hip_atomic_store(&st->front, f, __ATOMIC_RELAXED, HG_AGENT);
@@ -313,9 +331,17 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   // pair-major items (all blocks of the largest pair first), or round-major
   // under adaptive termination (round r of every pair before round r + 1)
   const bool adaptive = a.pst != nullptr;
-  const int r = static_cast<int>(adaptive ? item % a.n_pairs : item / a.n_hb);
-  const int hb = static_cast<int>(adaptive ? item / a.n_pairs : item % a.n_hb);
-  const int p = a.order ? a.order[r] : r;
+  int p, hb;
+  if (adaptive && a.iorder) {
+    // staggered round order (ransac_round_order_kernel); decoded into range
+    const uint32_t code = static_cast<uint32_t>(a.iorder[item]);
+    p = min(static_cast<int>(code / static_cast<uint32_t>(a.n_hb)), a.n_pairs - 1);
+    hb = static_cast<int>(code % static_cast<uint32_t>(a.n_hb));
+  } else {
+    const int r = static_cast<int>(adaptive ? item % a.n_pairs : item / a.n_hb);
+    hb = static_cast<int>(adaptive ? item / a.n_pairs : item % a.n_hb);
+    p = a.order ? a.order[r] : r;
+  }
   int64_t base;
   uint32_t n;
   pair_range(a, p, base, n);
@@ -510,6 +536,42 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
     }
   }
   if (p < a.n_pairs) order[r] = p;
+}
+
+// Queue order of the adaptive rounds. Round r of pair p is placed by
+// (2r + 1) / N_p, the midpoint of that round on a clock where each of the
+// pair's rounds takes N_p units (ties: lower pair index first). The rounds of
+// a large pair are spread over the queue instead of being stacked at its end,
+// so that the last items are rounds of small pairs; rounds of small pairs
+// come later than under plain round order, when more stopping points are
+// known. One wave per item: its position is the number of items placed before
+// it, counted exactly in integers over all pairs.
+__global__ __launch_bounds__(kThreads) void ransac_round_order_kernel(RansacArgs a) {
+  const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t total = static_cast<int64_t>(a.n_pairs) * a.n_hb;
+  if (item >= total) return;   // uniform across the wave
+  const int p = static_cast<int>(item / a.n_hb);
+  const int64_t r = item % a.n_hb;
+  int64_t b;
+  uint32_t n;
+  pair_range(a, p, b, n);
+  const int64_t np = max(n, 1u);
+  const int64_t R = a.n_hb;
+  int64_t pos = 0;
+  for (int q = lane; q < a.n_pairs; q += 64) {
+    pair_range(a, q, b, n);
+    const int64_t x = (2 * r + 1) * static_cast<int64_t>(max(n, 1u));
+    const int64_t c = (x + np - 1) / np;   // ceil(x / np)
+    // rounds r' of pair q with (2r' + 1) / N_q < (2r + 1) / N_p: the odd numbers below x / np
+    pos += min(R, c / 2);
+    // equal position: the round (c - 1) / 2 of a lower-numbered pair goes first
+    if (q < p && c * np == x && (c & 1) && (c - 1) / 2 < R) pos += 1;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pos += __shfl_xor(pos, o);
+  if (lane == 0 && pos >= 0 && pos < total)
+    a.iorder[pos] = static_cast<int32_t>(static_cast<int64_t>(p) * a.n_hb + r);
 }
 
 // ---- plain single-pair form -------------------------------------------------
@@ -756,6 +818,7 @@ static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, i
   a.pst = nullptr;
   a.rkey = nullptr;
   a.rdone = nullptr;
+  a.iorder = nullptr;
   a.n_eval = nullptr;
   a.one_minus_conf = 0.0;
   return a;
@@ -774,6 +837,13 @@ static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void 
   hipLaunchKernelGGL(ransac_prep_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads),
                      dim3(kThreads), 0, s, a, rank);
   if (int st = launched("ransac_prep_kernel")) return st;
+  if (a.iorder) {
+    const int64_t waves = static_cast<int64_t>(a.n_pairs) * a.n_hb;
+    const int64_t blocks = (waves + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(ransac_round_order_kernel, dim3(static_cast<unsigned>(blocks)),
+                       dim3(kThreads), 0, s, a);
+    if (int st = launched("ransac_round_order_kernel")) return st;
+  }
   KernelFn k = pick_kernel<true>(t.pts_per_lane, t.hyps_per_block);
   if (!k) return fail(HG_EINVAL, "unsupported tuning");
   const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(device_cus()) * t.blocks_per_cu,
@@ -984,7 +1054,13 @@ constexpr int kRound = 64;   // hypotheses per round (one work item)
 static size_t adaptive_extra_bytes(int n_pairs, int n_hyp) {
   const int64_t nr = (static_cast<int64_t>(n_hyp) + kRound - 1) / kRound;
   return align256(sizeof(PairState) * static_cast<size_t>(n_pairs)) +
-         align256(8ull * n_pairs * nr) + align256(4ull * n_pairs * nr);
+         align256(8ull * n_pairs * nr) + 2 * align256(4ull * n_pairs * nr);
+}
+
+// The staggered round order costs n_pairs^2 * rounds integer steps: used up
+// to 2^27 of them (e.g. 2048 pairs of 1024 hypotheses), round order beyond.
+static bool stagger_rounds(int64_t n_pairs, int64_t n_rounds) {
+  return n_pairs * n_pairs * n_rounds <= (int64_t(1) << 27);
 }
 
 extern "C" size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max) {
@@ -1018,6 +1094,8 @@ extern "C" int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *
   a.rkey = reinterpret_cast<unsigned long long *>(x);
   x += align256(8ull * n_pairs * a.n_hb);
   a.rdone = reinterpret_cast<uint32_t *>(x);
+  x += align256(4ull * n_pairs * a.n_hb);
+  if (stagger_rounds(n_pairs, a.n_hb)) a.iorder = reinterpret_cast<int32_t *>(x);
   a.n_eval = n_evaluated;
   a.one_minus_conf = 1.0 - confidence;
   return launch_batched(a, t, ws, as_stream(stream));

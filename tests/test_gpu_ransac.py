@@ -313,6 +313,39 @@ def test_adaptive_extremes():
         check_adaptive_pair(corr[:, a:b], 700, 3, p, got, f"extreme {p}")
 
 
+def test_adaptive_equal_and_odd_ratio_sizes():
+    """Pairs of 300, 900 and 1500 points (equal sizes, and size ratios 3 and 5,
+    give rounds with equal queue keys): every pair finishes, at the oracle's
+    stopping round, with the oracle's result, for two tunings alike."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    sizes = [300, 900, 1500, 300, 300, 900, 1500, 1500, 900, 300, 300, 900]
+    ratios = [0.25, 0.5, 0.3, 0.9, 0.2, 0.35, 0.6, 0.22, 0.8, 0.4, 0.3, 0.25]
+    sets = [synth.correspondences(n, r, 200 + i) for i, (n, r) in enumerate(zip(sizes, ratios))]
+    corr = np.ascontiguousarray(np.concatenate([s.corr for s in sets], axis=1))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ar = hgpu.AdaptiveRansac(torch.from_numpy(corr).cuda(), torch.from_numpy(off).cuda(), 1000,
+                             TAU, 29, confidence=0.99)
+    ref = None
+    for tune in ((16, 64, 4), (8, 64, 1)):
+        announce(f"adaptive equal/odd-ratio sizes tuning {tune}")
+        ar.run(tune)
+        torch.cuda.synchronize()
+        out = dict(best_H=ar.best_H.cpu().numpy(), best_count=ar.best_count.cpu().numpy(),
+                   best_hyp=ar.best_hyp.cpu().numpy(), n_eval=ar.n_evaluated.cpu().numpy(),
+                   mask=ar.mask.cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            for k in ref:
+                assert np.array_equal(ref[k], out[k]), (k, tune)
+    for p in range(len(sizes)):
+        a, b = off[p], off[p + 1]
+        got = dict(best_H=ref["best_H"][p], best_count=ref["best_count"][p],
+                   best_hyp=ref["best_hyp"][p], n_eval=ref["n_eval"][p], mask=ref["mask"][a:b])
+        check_adaptive_pair(corr[:, a:b], 1000, 29, p, got, f"equal-size pair {p}")
+
+
 def test_batched_rejects_bad_offsets():
     """Offsets are checked on the host before any launch: decreasing, out of
     range, or a pair with fewer than 4 points is refused."""

@@ -95,6 +95,22 @@ def test_small_patches_against_oracle(fused):
     assert rel(g[:4], fd).max() < FD_TOL
 
 
+def test_other_patch_sizes():
+    """Sizes other than the benchmark's: 150 x 140 and 33 x 45 (w not a
+    multiple of 4), fused and separate stages, against the oracle."""
+    require_gpu()
+    for B, h, w, seed in ((3, 150, 140, 31), (4, 33, 45, 32)):
+        rng = np.random.default_rng(seed)
+        pbl = type("PB", (), {})()
+        pbl.img = rng.normal(size=(B, h, w)).astype(np.float32)
+        pbl.tgt = rng.normal(size=(B, h, w)).astype(np.float32)
+        pbl.offsets = rng.uniform(-6, 6, (B, 4, 2)).astype(np.float32)
+        announce(f"warp-l1 fwd+bwd {B} patches {h}x{w}")
+        for fused in (True, False):
+            L, g = run_pipeline(pbl, fused=fused)
+            compare_oracle(pbl, L, g, slice(None), f"{h}x{w} fused={fused}")
+
+
 def test_ragged_sizes_and_stored_form():
     require_gpu()
     import paper_2402_18008_amd as hgpu

@@ -487,32 +487,33 @@ __global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
 // Resets keys, done counters and the queue, and ranks pairs by size (largest
 // first, ties by index). Pair q's sort key is (N_q << 32) | ~q, unique per
 // pair, so the rank of p (the number of larger keys) is a permutation of
-// 0 .. n_pairs - 1. Each thread ranks one pair against all keys, staged
-// through LDS in tiles of kThreads and compared two per 16-byte read.
+// 0 .. n_pairs - 1. One wave ranks one pair; the keys are staged through LDS
+// in tiles of kThreads, shared by the workgroup's waves. Launched with one
+// wave per pair (at least one workgroup).
 __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int rank) {
-  __shared__ __attribute__((aligned(16))) unsigned long long tile[kThreads];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && a.queue) *a.queue = 0u;
-  if (p < a.n_pairs) {
-    if (a.keys) a.keys[p] = 0ull;
-    if (a.done) a.done[p] = 0u;
+  __shared__ unsigned long long tile[kThreads];
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  if (g == 0 && a.queue) *a.queue = 0u;
+  for (int64_t q = g; q < a.n_pairs; q += stride) {
+    if (a.keys) a.keys[q] = 0ull;
+    if (a.done) a.done[q] = 0u;
     if (a.pst) {
-      a.pst[p].best = 0ull;
-      a.pst[p].front = 0u;
-      a.pst[p].stop = static_cast<uint32_t>(a.n_hb);
-      a.pst[p].lock = 0u;
-      a.pst[p].finished = 0u;
+      a.pst[q].best = 0ull;
+      a.pst[q].front = 0u;
+      a.pst[q].stop = static_cast<uint32_t>(a.n_hb);
+      a.pst[q].lock = 0u;
+      a.pst[q].finished = 0u;
     }
   }
   if (a.rdone) {
     const int64_t total = static_cast<int64_t>(a.n_pairs) * a.n_hb;
-    for (int64_t i = p; i < total; i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-      a.rdone[i] = 0u;
+    for (int64_t i = g; i < total; i += stride) a.rdone[i] = 0u;
   }
   if (!a.order) return;
   int32_t *order = const_cast<int32_t *>(a.order);
   if (!rank) {
-    if (p < a.n_pairs) order[p] = p;
+    for (int64_t q = g; q < a.n_pairs; q += stride) order[q] = static_cast<int32_t>(q);
     return;
   }
   auto sort_key = [&](int q) {
@@ -521,6 +522,8 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
     pair_range(a, q, b, n);
     return (static_cast<unsigned long long>(n) << 32) | (0xFFFFFFFFu - static_cast<uint32_t>(q));
   };
+  const int p = static_cast<int>(g >> 6);   // this wave's pair (uniform across the wave)
+  const int lane = threadIdx.x & 63;
   const unsigned long long kp = p < a.n_pairs ? sort_key(p) : ~0ull;
   int r = 0;
   for (int q0 = 0; q0 < a.n_pairs; q0 += kThreads) {
@@ -528,14 +531,11 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
     __syncthreads();
     tile[threadIdx.x] = q < a.n_pairs ? sort_key(q) : 0ull;   // 0: below every real key
     __syncthreads();
-    const ulonglong2 *t2 = reinterpret_cast<const ulonglong2 *>(tile);
-#pragma unroll 8
-    for (int k = 0; k < kThreads / 2; ++k) {
-      const ulonglong2 v = t2[k];
-      r += (v.x > kp) + (v.y > kp);
-    }
+    for (int k = lane; k < kThreads; k += 64) r += tile[k] > kp ? 1 : 0;
   }
-  if (p < a.n_pairs) order[r] = p;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+  if (p < a.n_pairs && lane == 0) order[r] = p;
 }
 
 // Queue order of the adaptive rounds. Round r of pair p is placed by
@@ -547,30 +547,52 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
 // known. One wave per item: its position is the number of items placed before
 // it, counted exactly in integers over all pairs.
 __global__ __launch_bounds__(kThreads) void ransac_round_order_kernel(RansacArgs a) {
+  __shared__ int64_t nsz[kThreads];
   const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t total = static_cast<int64_t>(a.n_pairs) * a.n_hb;
-  if (item >= total) return;   // uniform across the wave
-  const int p = static_cast<int>(item / a.n_hb);
-  const int64_t r = item % a.n_hb;
+  const bool live = item < total;   // uniform across the wave
+  const int p = live ? static_cast<int>(item / a.n_hb) : 0;
+  const int64_t r = live ? item % a.n_hb : 0;
   int64_t b;
   uint32_t n;
   pair_range(a, p, b, n);
   const int64_t np = max(n, 1u);
+  const double inv = 1.0 / static_cast<double>(np);
   const int64_t R = a.n_hb;
+  const int64_t cap = (2 * R + 2) * np;   // x >= cap: every round of q comes first
   int64_t pos = 0;
-  for (int q = lane; q < a.n_pairs; q += 64) {
-    pair_range(a, q, b, n);
-    const int64_t x = (2 * r + 1) * static_cast<int64_t>(max(n, 1u));
-    const int64_t c = (x + np - 1) / np;   // ceil(x / np)
-    // rounds r' of pair q with (2r' + 1) / N_q < (2r + 1) / N_p: the odd numbers below x / np
-    pos += min(R, c / 2);
-    // equal position: the round (c - 1) / 2 of a lower-numbered pair goes first
-    if (q < p && c * np == x && (c & 1) && (c - 1) / 2 < R) pos += 1;
+  // pair sizes staged through LDS, kThreads at a time, shared by the workgroup's waves
+  for (int q0 = 0; q0 < a.n_pairs; q0 += kThreads) {
+    __syncthreads();
+    if (q0 + static_cast<int>(threadIdx.x) < a.n_pairs) {
+      pair_range(a, q0 + threadIdx.x, b, n);
+      nsz[threadIdx.x] = max(n, 1u);
+    }
+    __syncthreads();
+    const int qn = min(kThreads, a.n_pairs - q0);
+    for (int k = lane; k < qn; k += 64) {
+      const int64_t x = (2 * r + 1) * nsz[k];
+      if (x >= cap) {
+        pos += R;
+        continue;
+      }
+      // c = ceil(x / np): the double estimate is within one of it (x / np < 2R + 2),
+      // and one exact integer step corrects it
+      int64_t c = static_cast<int64_t>(ceil(static_cast<double>(x) * inv));
+      if ((c - 1) * np >= x)
+        --c;
+      else if (c * np < x)
+        ++c;
+      // rounds r' of pair q with (2r' + 1) / N_q < (2r + 1) / N_p: the odd numbers below x / np
+      pos += min(R, c / 2);
+      // equal position: the round (c - 1) / 2 of a lower-numbered pair goes first
+      if (q0 + k < p && c * np == x && (c & 1) && (c - 1) / 2 < R) pos += 1;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) pos += __shfl_xor(pos, o);
-  if (lane == 0 && pos >= 0 && pos < total)
+  if (live && lane == 0 && pos >= 0 && pos < total)
     a.iorder[pos] = static_cast<int32_t>(static_cast<int64_t>(p) * a.n_hb + r);
 }
 
@@ -834,7 +856,10 @@ static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void 
   a.queue = w.queue;
   a.order = w.order;
   const int rank = a.n_pairs <= 65536 ? 1 : 0;
-  hipLaunchKernelGGL(ransac_prep_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads),
+  // one wave per pair when ranking (ranks of 65536 pairs: 16384 workgroups)
+  const int64_t prep_blocks = rank ? (static_cast<int64_t>(a.n_pairs) + kWaves - 1) / kWaves
+                                   : (static_cast<int64_t>(a.n_pairs) + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(ransac_prep_kernel, dim3(static_cast<unsigned>(prep_blocks)),
                      dim3(kThreads), 0, s, a, rank);
   if (int st = launched("ransac_prep_kernel")) return st;
   if (a.iorder) {

@@ -2,19 +2,25 @@
 //
 // Work item = (pair, block of HB hypotheses). A 256-thread workgroup solves
 // its HB hypotheses (one per thread) into LDS, then scores them against the
-// pair's points: each lane holds P correspondences in registers, the
-// hypothesis is broadcast to scalar registers, the inlier test runs per
-// (hypothesis, point) and counts come from a wavefront ballot + popcount.
-// The per-pair argmax is an atomicMax on a packed (count, ~index) key; the last
-// workgroup to finish a pair recomputes the winning hypothesis and writes the
-// pair's inlier mask and best outputs.
+// pair's points: each lane holds P correspondences in registers, every lane
+// reads the hypothesis from LDS, the inlier test runs per (hypothesis, point)
+// and counts come from a wavefront ballot + popcount. The argmax is over a
+// packed (count, ~index) key.
 //
 // Forms:
 //  * fused single pair: grid = hypothesis blocks, each writing its best key;
 //    a second kernel reduces them and writes the mask;
 //  * plain single pair: solve all -> H buffer, score, argmax, mask kernels;
 //  * batched persistent: CUs x blocks_per_cu workgroups drain an atomic queue
-//    of items ordered by pair size (largest first).
+//    of items ordered by pair size (largest first); each item atomicMax-es its
+//    key into the pair's; a finish kernel (one workgroup per pair) then
+//    recomputes each winner and writes the outputs and masks;
+//  * adaptive termination: items are rounds of 64 hypotheses; each writes its
+//    round key into a write-once slot and may advance an advisory prefix that
+//    lets later rounds be skipped; the finish kernel applies the stopping rule
+//    to the slots in order.
+// Workgroups exchange nothing but atomics whose results the finish kernel
+// reads after the launch boundary, so no fences are needed.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -51,30 +57,38 @@ struct RansacArgs {
   uint8_t *mask;
   int32_t *hyp_counts;     // may be null
   unsigned long long *keys;
-  uint32_t *done;
   uint32_t *queue;
   const int32_t *order;    // pair processing order (largest first), or nullptr
   float *hbuf;             // single pair: every hypothesis's H (9 floats), or nullptr
   unsigned long long *blockbest;   // single pair: best key of each work item, or nullptr
   // adaptive termination (nullptr pst = off): work items are rounds of HB
-  // hypotheses in round-major order; per pair and round the round's best key
-  // and a completion flag; per pair the merged-prefix state
+  // hypotheses; per pair and round the round's best key (write-once slot);
+  // per pair the advisory prefix and stopping hint
   struct PairState *pst;
   unsigned long long *rkey;
-  uint32_t *rdone;
   int32_t *iorder;         // adaptive: queue position -> pair * n_hb + round, or NULL
   int32_t *n_eval;
   double one_minus_conf;
 };
 
-// Merged-prefix state of one pair under adaptive termination. `front` rounds
-// have been merged into `best`; `stop` is the number of rounds after which the
-// stopping rule holds (initially all rounds); only the holder of `lock` reads
-// or writes front, best and finished.
+// Advisory state of one pair under adaptive termination, read and written
+// only with relaxed atomics. `prefix` = (front << 32) | best count over rounds
+// [0, front), extended in order from published round keys (monotone in both
+// halves, so atomicMax keeps the furthest one); `stop` = a number of rounds
+// after which no round is needed (an exact stopping point or a bound on it;
+// atomicMin). Rounds at or past `stop` are skipped or abandoned. Nothing here
+// decides a result: the finish kernel re-applies the rule to the published
+// round keys in order.
 struct PairState {
-  unsigned long long best;
-  uint32_t front, stop, lock, finished;
+  unsigned long long prefix;
+  uint32_t stop, pad;
 };
+
+// Round key slot not yet published (no real key has all bits set).
+constexpr unsigned long long kUnpublished = ~0ull;
+
+// Hypotheses per round under adaptive termination (one work item).
+constexpr int kRoundHyps = 64;
 
 __device__ __forceinline__ void pair_range(const RansacArgs &a, int p, int64_t &base, uint32_t &n) {
   if (a.off) {
@@ -103,11 +117,12 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // among the points [base, base + n) held in registers (P per lane); each wave
 // adds its counts into cnt[h] (LDS atomics). TAIL: the chunk runs past n and
 // lanes beyond it are masked out of the ballots.
-// Under adaptive termination `stop` points at the pair's stopping round and
-// `hb` is this item's round: every 8 hypotheses the wave re-reads it and gives
-// up a round that is no longer needed (returns false). The stopping round only
-// ever decreases and rounds at or past it are never merged, so an abandoned
-// round changes no result.
+// Under adaptive termination `stop` points at the pair's stopping hint and
+// `hb` is this item's round: every 8 hypotheses the wave compares hb with the
+// value it loaded at the previous check (the load's latency overlaps the 8
+// hypotheses) and gives up a round that is no longer needed (returns false).
+// Rounds at or past the hint are never needed, so an abandoned round changes
+// no result.
 template <int P, bool TAIL>
 __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
                                             const float *X2, const float *Y2, uint32_t c0,
@@ -128,10 +143,13 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
     y2[p] = Y2[j] * a.inv_tau;
     if (TAIL) live[p] = __ballot(i < n);
   }
+  uint32_t stop_seen =
+      stop ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   for (int h = 0; h < nh; ++h) {
-    if (stop && (h & 7) == 7 &&
-        hb >= __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return false;
+    if (stop && (h & 7) == 7) {
+      if (hb >= stop_seen) return false;
+      stop_seen = __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (!((vmask >> h) & 1ull)) continue;
     // H read from LDS by every lane (one address: a broadcast) and used from
     // vector registers; scalar copies would cost a readfirstlane per entry and
@@ -213,69 +231,48 @@ __device__ __forceinline__ bool enough_samples(uint32_t best_count, uint32_t n, 
 
 #define HG_AGENT __HIP_MEMORY_SCOPE_AGENT
 
-// Called by one thread after its round's key is published: merges completed
-// rounds in order (under the pair's lock) and applies the stopping rule.
-// Returns true for exactly one caller per pair: the one whose merge reached the
-// stopping round; it receives the final key and the number of hypotheses
-// evaluated. A caller that finds the lock taken leaves: the holder re-checks
-// for newly completed rounds after releasing it.
-__device__ bool adaptive_advance(const RansacArgs &a, int p, uint32_t n_pts, int HB,
-                                 unsigned long long &key_out, int32_t &neval_out) {
+__device__ __forceinline__ uint32_t key_count(unsigned long long k) {
+  return k ? static_cast<uint32_t>((k >> 32) - 1ull) : 0u;
+}
+
+// Called by one thread after round hb of pair p published `key`. If hb is the
+// pair's front, extends the merged prefix over the rounds published since
+// (in order), applies the stopping rule at each step, and lowers `stop` to
+// the stopping point when it holds, else to the bound that the prefix's best
+// count gives (the count only grows and the rule is monotone in it, so the
+// rule holds at the latest there). Every value read is final (a slot is
+// written once per launch) or the sentinel, so a stale read only means a
+// shorter prefix, never a wrong one.
+__device__ void adaptive_hint(const RansacArgs &a, int p, uint32_t n_pts, int HB, int hb,
+                              unsigned long long key) {
   PairState *st = a.pst + p;
-  const uint32_t nr = static_cast<uint32_t>(a.n_hb);
-  unsigned long long *rkey = a.rkey + static_cast<int64_t>(p) * nr;
-  uint32_t *rdone = a.rdone + static_cast<int64_t>(p) * nr;
+  const unsigned long long w = __hip_atomic_load(&st->prefix, __ATOMIC_RELAXED, HG_AGENT);
+  uint32_t f = static_cast<uint32_t>(w >> 32);
+  if (f != static_cast<uint32_t>(hb)) return;
+  uint32_t bc = static_cast<uint32_t>(w);
+  uint32_t s = __hip_atomic_load(&st->stop, __ATOMIC_RELAXED, HG_AGENT);
+  const uint32_t n_hyp = static_cast<uint32_t>(a.n_hyp);
+  const unsigned long long *rk = a.rkey + static_cast<int64_t>(p) * a.n_hb;
+  unsigned long long k = key;
   for (;;) {
-    uint32_t expected = 0u;
-    if (!__hip_atomic_compare_exchange_strong(&st->lock, &expected, 1u, __ATOMIC_SEQ_CST,
-                                              __ATOMIC_SEQ_CST, HG_AGENT))
-      return false;
-    uint32_t f = __hip_atomic_load(&st->front, __ATOMIC_RELAXED, HG_AGENT);
-    uint32_t s = __hip_atomic_load(&st->stop, __ATOMIC_RELAXED, HG_AGENT);
-    unsigned long long best = __hip_atomic_load(&st->best, __ATOMIC_RELAXED, HG_AGENT);
-    const uint32_t finished = __hip_atomic_load(&st->finished, __ATOMIC_RELAXED, HG_AGENT);
-    const uint32_t f0 = f;
-    while (f < s && __hip_atomic_load(&rdone[f], __ATOMIC_SEQ_CST, HG_AGENT) != 0u) {
-      const unsigned long long k = __hip_atomic_load(&rkey[f], __ATOMIC_RELAXED, HG_AGENT);
-      best = k > best ? k : best;
-      ++f;
-      const uint32_t m = min(f * static_cast<uint32_t>(HB), static_cast<uint32_t>(a.n_hyp));
-      const uint32_t bc = best ? static_cast<uint32_t>((best >> 32) - 1ull) : 0u;
-      if (m >= static_cast<uint32_t>(a.n_hyp) || enough_samples(bc, n_pts, m, a.one_minus_conf)) {
-        s = f;
-        __hip_atomic_store(&st->stop, s, __ATOMIC_RELAXED, HG_AGENT);
-      }
+    bc = max(bc, key_count(k));
+    ++f;
+    const uint32_t m = min(f * static_cast<uint32_t>(HB), n_hyp);
+    if (m >= n_hyp || enough_samples(bc, n_pts, m, a.one_minus_conf)) {
+      s = min(s, f);
+      break;
     }
-    if (f > f0 && f < s) {
-      // The best count only grows and the rule is monotone in it (for a fixed
-      // number of hypotheses), so the rule will hold at the latest after the
-      // first round at which it holds with the current best: later rounds
-      // are never merged, and lowering `stop` to there lets the workgroups skip
-      // or abandon them. The merge above then ends on the rule, as before.
-      const uint32_t bc = best ? static_cast<uint32_t>((best >> 32) - 1ull) : 0u;
-      for (uint32_t c = f + 1u; c < s; ++c) {
-        const uint32_t m = min(c * static_cast<uint32_t>(HB), static_cast<uint32_t>(a.n_hyp));
-        if (enough_samples(bc, n_pts, m, a.one_minus_conf)) {
-          s = c;
-          __hip_atomic_store(&st->stop, s, __ATOMIC_RELAXED, HG_AGENT);
-          break;
-        }
-      }
-    }
-    __hip_atomic_store(&st->front, f, __ATOMIC_RELAXED, HG_AGENT);
-    __hip_atomic_store(&st->best, best, __ATOMIC_RELAXED, HG_AGENT);
-    const bool done_now = f >= s && finished == 0u;
-    if (done_now) __hip_atomic_store(&st->finished, 1u, __ATOMIC_RELAXED, HG_AGENT);
-    __hip_atomic_store(&st->lock, 0u, __ATOMIC_SEQ_CST, HG_AGENT);
-    if (done_now) {
-      key_out = best;
-      neval_out = static_cast<int32_t>(min(s * static_cast<uint32_t>(HB),
-                                           static_cast<uint32_t>(a.n_hyp)));
-      return true;
-    }
-    // a round may have completed while the lock was held: merge it too
-    if (!(f < s && __hip_atomic_load(&rdone[f], __ATOMIC_SEQ_CST, HG_AGENT) != 0u)) return false;
+    if (f >= s) break;
+    k = __hip_atomic_load(&rk[f], __ATOMIC_RELAXED, HG_AGENT);
+    if (k == kUnpublished) break;
   }
+  for (uint32_t c = f + 1u; c < s; ++c)
+    if (enough_samples(bc, n_pts, min(c * static_cast<uint32_t>(HB), n_hyp), a.one_minus_conf)) {
+      s = c;
+      break;
+    }
+  atomicMax(&st->prefix, (static_cast<unsigned long long>(f) << 32) | bc);
+  atomicMin(&st->stop, s);
 }
 
 // Shared memory of one workgroup.
@@ -284,46 +281,9 @@ struct Smem {
   float H[HB][9];          // scoring form (rows 1-2 scaled by 1/tau)
   uint32_t valid[HB];
   uint32_t cnt[HB];
-  float bestH[9];
   int64_t item;
-  uint32_t last;
   uint32_t skip;
-  int32_t neval;
-  unsigned long long key;
 };
-
-// Writes the inlier mask and best outputs of pair p (whole workgroup).
-template <int HB>
-__device__ void finish_pair(const RansacArgs &a, int p, int64_t base, uint32_t n, Smem<HB> &sm) {
-  if (threadIdx.x == 0) {
-    const unsigned long long key = sm.key;
-    if (a.n_eval) a.n_eval[p] = sm.neval;
-    if (key != 0ull) {
-      const uint32_t hyp = 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
-      // the winner is recomputed (same device function, same bits) rather than read
-      // from another workgroup's memory
-      make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, hyp, static_cast<uint32_t>(p),
-                      sm.bestH);
-      a.best_count[p] = static_cast<int32_t>((key >> 32) - 1ull);
-      a.best_hyp[p] = static_cast<int32_t>(hyp);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) sm.bestH[k] = 0.0f;
-      a.best_count[p] = 0;
-      a.best_hyp[p] = -1;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 9) a.best_H[9 * p + threadIdx.x] = sm.bestH[threadIdx.x];
-  const bool any = sm.key != 0ull;
-  float hh[9];
-  score_form(sm.bestH, a.inv_tau, hh);
-  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
-  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
-  for (uint32_t i = threadIdx.x; i < n; i += kThreads)
-    a.mask[base + i] =
-        (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
-}
 
 // Process one work item: pair rank r, hypothesis block hb.
 template <int P, int HB>
@@ -407,32 +367,18 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
       if (a.blockbest) {
         a.blockbest[item] = key;     // reduced by the mask kernel
       } else if (adaptive) {
-        const int64_t slot = static_cast<int64_t>(p) * a.n_hb + hb;
-        __hip_atomic_store(&a.rkey[slot], key, __ATOMIC_RELAXED, HG_AGENT);
-        __hip_atomic_store(&a.rdone[slot], 1u, __ATOMIC_SEQ_CST, HG_AGENT);
-        unsigned long long fk = 0ull;
-        int32_t ne = 0;
-        sm.last = adaptive_advance(a, p, n, HB, fk, ne) ? 1u : 0u;
-        sm.key = fk;
-        sm.neval = ne;
-      } else {
-        if (key != 0ull) atomicMax(&a.keys[p], key);
-        // release this block's results, then count it; the last block of the pair
-        // (all blocks' keys are in) writes the pair's mask
-        __threadfence();
-        const bool last = atomicAdd(&a.done[p], 1u) == static_cast<uint32_t>(a.n_hb - 1);
-        sm.last = last ? 1u : 0u;
-        if (last) {
-          __threadfence();
-          sm.key = atomicMax(&a.keys[p], 0ull);   // coherent read of the final key
-          sm.neval = a.n_hyp;
-        }
+        // write-once slot, then the advisory prefix / stopping hint
+        __hip_atomic_store(&a.rkey[static_cast<int64_t>(p) * a.n_hb + hb], key, __ATOMIC_RELAXED,
+                           HG_AGENT);
+        adaptive_hint(a, p, n, HB, hb, key);
+      } else if (key != 0ull) {
+        atomicMax(&a.keys[p], key);  // the pair's outputs come from the finish kernel
       }
     }
   }
-  if (a.blockbest) return;
-  __syncthreads();
-  if (sm.last) finish_pair<HB>(a, p, base, n, sm);
+  // Every wave leaves the item here together. Without this barrier the
+  // thread-0-only tail above may be folded into the persistent loop so that
+  // waves execute the loop's barriers different numbers of times.
   __syncthreads();
 }
 
@@ -451,6 +397,69 @@ __global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
     if (item >= a.n_items) break;
     run_item<P, HB>(a, item, sm);
   }
+}
+
+// After the persistent kernel (whose keys are then all visible): one workgroup
+// per pair writes the pair's best hypothesis, count, index, hypotheses
+// evaluated and inlier mask. Fixed count: the pair's key is the atomicMax of
+// its blocks' keys. Adaptive termination: the stopping rule applied to the
+// published round keys in order, as a sequential loop would (a round before
+// the stopping point is always published; if one were missing, n_evaluated
+// would read -1).
+__global__ __launch_bounds__(kThreads) void ransac_finish_kernel(RansacArgs a) {
+  __shared__ float bestH[9];
+  __shared__ unsigned long long skey;
+  const int p = blockIdx.x;
+  int64_t base;
+  uint32_t n;
+  pair_range(a, p, base, n);
+  if (threadIdx.x == 0) {
+    unsigned long long key = 0ull;
+    int32_t ne = a.n_hyp;
+    if (a.pst) {
+      ne = -1;
+      const uint32_t n_hyp = static_cast<uint32_t>(a.n_hyp);
+      const unsigned long long *rk = a.rkey + static_cast<int64_t>(p) * a.n_hb;
+      for (int f = 0; f < a.n_hb; ++f) {
+        const unsigned long long k = rk[f];
+        if (k == kUnpublished) break;
+        key = max(key, k);
+        const uint32_t m = min(static_cast<uint32_t>(f + 1) * static_cast<uint32_t>(kRoundHyps),
+                               n_hyp);
+        if (m >= n_hyp || enough_samples(key_count(key), n, m, a.one_minus_conf)) {
+          ne = static_cast<int32_t>(m);
+          break;
+        }
+      }
+    } else {
+      key = a.keys[p];
+    }
+    if (a.n_eval) a.n_eval[p] = ne;
+    if (key != 0ull) {
+      const uint32_t hyp = 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
+      // the winner is recomputed (same device function, same bits) rather than read
+      // from another workgroup's memory
+      make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, hyp, static_cast<uint32_t>(p), bestH);
+      a.best_count[p] = static_cast<int32_t>(key_count(key));
+      a.best_hyp[p] = static_cast<int32_t>(hyp);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) bestH[k] = 0.0f;
+      a.best_count[p] = 0;
+      a.best_hyp[p] = -1;
+    }
+    skey = key;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) a.best_H[9 * p + threadIdx.x] = bestH[threadIdx.x];
+  const bool any = skey != 0ull;
+  float hh[9];
+  score_form(bestH, a.inv_tau, hh);
+  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
+  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
+  for (uint32_t i = threadIdx.x; i < n; i += kThreads)
+    a.mask[base + i] =
+        (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
 }
 
 // Single pair, after the fused kernel: reduce the work items' best keys (every
@@ -484,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
     a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
 }
 
-// Resets keys, done counters and the queue, and ranks pairs by size (largest
+// Resets keys, the queue and the adaptive state, and ranks pairs by size (largest
 // first, ties by index). Pair q's sort key is (N_q << 32) | ~q, unique per
 // pair, so the rank of p (the number of larger keys) is a permutation of
 // 0 .. n_pairs - 1. One wave ranks one pair; the keys are staged through LDS
@@ -497,18 +506,15 @@ __global__ __launch_bounds__(kThreads) void ransac_prep_kernel(RansacArgs a, int
   if (g == 0 && a.queue) *a.queue = 0u;
   for (int64_t q = g; q < a.n_pairs; q += stride) {
     if (a.keys) a.keys[q] = 0ull;
-    if (a.done) a.done[q] = 0u;
     if (a.pst) {
-      a.pst[q].best = 0ull;
-      a.pst[q].front = 0u;
+      a.pst[q].prefix = 0ull;
       a.pst[q].stop = static_cast<uint32_t>(a.n_hb);
-      a.pst[q].lock = 0u;
-      a.pst[q].finished = 0u;
+      a.pst[q].pad = 0u;
     }
   }
-  if (a.rdone) {
+  if (a.rkey) {
     const int64_t total = static_cast<int64_t>(a.n_pairs) * a.n_hb;
-    for (int64_t i = g; i < total; i += stride) a.rdone[i] = 0u;
+    for (int64_t i = g; i < total; i += stride) a.rkey[i] = kUnpublished;
   }
   if (!a.order) return;
   int32_t *order = const_cast<int32_t *>(a.order);
@@ -764,13 +770,12 @@ static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255);
 
 struct BatchedWs {
   unsigned long long *keys;
-  uint32_t *done;
   int32_t *order;
   uint32_t *queue;
 };
 
 static size_t batched_ws_bytes(int n_pairs) {
-  return align256(8ull * n_pairs) + align256(4ull * n_pairs) + align256(4ull * n_pairs) + 256;
+  return align256(8ull * n_pairs) + align256(4ull * n_pairs) + 256;
 }
 
 static BatchedWs carve_batched(void *ws, int n_pairs) {
@@ -778,8 +783,6 @@ static BatchedWs carve_batched(void *ws, int n_pairs) {
   BatchedWs w;
   w.keys = reinterpret_cast<unsigned long long *>(p);
   p += align256(8ull * n_pairs);
-  w.done = reinterpret_cast<uint32_t *>(p);
-  p += align256(4ull * n_pairs);
   w.order = reinterpret_cast<int32_t *>(p);
   p += align256(4ull * n_pairs);
   w.queue = reinterpret_cast<uint32_t *>(p);
@@ -832,27 +835,25 @@ static RansacArgs make_args(const float *corr, int64_t ld, const int64_t *off, i
   a.mask = mask;
   a.hyp_counts = hyp_counts;
   a.keys = nullptr;
-  a.done = nullptr;
   a.queue = nullptr;
   a.order = nullptr;
   a.hbuf = nullptr;
   a.blockbest = nullptr;
   a.pst = nullptr;
   a.rkey = nullptr;
-  a.rdone = nullptr;
   a.iorder = nullptr;
   a.n_eval = nullptr;
   a.one_minus_conf = 0.0;
   return a;
 }
 
-// Enqueue the batched form (prep + persistent kernel) on stream s.
+// Enqueue the batched form (prep, round order, persistent kernel, finish) on
+// stream s.
 static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void *ws,
                           hipStream_t s) {
   RansacArgs a = a0;
   const BatchedWs w = carve_batched(ws, a.n_pairs);
   a.keys = w.keys;
-  a.done = w.done;
   a.queue = w.queue;
   a.order = w.order;
   const int rank = a.n_pairs <= 65536 ? 1 : 0;
@@ -874,7 +875,10 @@ static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void 
   const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(device_cus()) * t.blocks_per_cu,
                                            std::max<int64_t>(1, a.n_items));
   hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, a);
-  return launched("ransac_kernel<persistent>");
+  if (int st = launched("ransac_kernel<persistent>")) return st;
+  hipLaunchKernelGGL(ransac_finish_kernel, dim3(static_cast<unsigned>(a.n_pairs)), dim3(kThreads),
+                     0, s, a);
+  return launched("ransac_finish_kernel");
 }
 
 static int check_batched(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
@@ -1074,12 +1078,12 @@ done:
 
 // ---- adaptive termination ---------------------------------------------------
 
-constexpr int kRound = 64;   // hypotheses per round (one work item)
+constexpr int kRound = kRoundHyps;
 
 static size_t adaptive_extra_bytes(int n_pairs, int n_hyp) {
   const int64_t nr = (static_cast<int64_t>(n_hyp) + kRound - 1) / kRound;
   return align256(sizeof(PairState) * static_cast<size_t>(n_pairs)) +
-         align256(8ull * n_pairs * nr) + 2 * align256(4ull * n_pairs * nr);
+         align256(8ull * n_pairs * nr) + align256(4ull * n_pairs * nr);
 }
 
 // The staggered round order costs n_pairs^2 * rounds integer steps: used up
@@ -1118,8 +1122,6 @@ extern "C" int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *
   x += align256(sizeof(PairState) * static_cast<size_t>(n_pairs));
   a.rkey = reinterpret_cast<unsigned long long *>(x);
   x += align256(8ull * n_pairs * a.n_hb);
-  a.rdone = reinterpret_cast<uint32_t *>(x);
-  x += align256(4ull * n_pairs * a.n_hb);
   if (stagger_rounds(n_pairs, a.n_hb)) a.iorder = reinterpret_cast<int32_t *>(x);
   a.n_eval = n_evaluated;
   a.one_minus_conf = 1.0 - confidence;

@@ -409,30 +409,64 @@ __global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
 __global__ __launch_bounds__(kThreads) void ransac_finish_kernel(RansacArgs a) {
   __shared__ float bestH[9];
   __shared__ unsigned long long skey;
+  __shared__ int32_t sne;
   const int p = blockIdx.x;
   int64_t base;
   uint32_t n;
   pair_range(a, p, base, n);
-  if (threadIdx.x == 0) {
-    unsigned long long key = 0ull;
-    int32_t ne = a.n_hyp;
-    if (a.pst) {
-      ne = -1;
-      const uint32_t n_hyp = static_cast<uint32_t>(a.n_hyp);
-      const unsigned long long *rk = a.rkey + static_cast<int64_t>(p) * a.n_hb;
-      for (int f = 0; f < a.n_hb; ++f) {
-        const unsigned long long k = rk[f];
-        if (k == kUnpublished) break;
-        key = max(key, k);
-        const uint32_t m = min(static_cast<uint32_t>(f + 1) * static_cast<uint32_t>(kRoundHyps),
-                               n_hyp);
-        if (m >= n_hyp || enough_samples(key_count(key), n, m, a.one_minus_conf)) {
-          ne = static_cast<int32_t>(m);
-          break;
-        }
+  if (a.pst && threadIdx.x < 64) {
+    // wave 0: 64 rounds at a time, in order; lane f holds round c0 + f, its
+    // prefix maximum (shuffle scan) and whether the rule holds after it
+    const int lane = threadIdx.x;
+    const uint32_t n_hyp = static_cast<uint32_t>(a.n_hyp);
+    const unsigned long long *rk = a.rkey + static_cast<int64_t>(p) * a.n_hb;
+    unsigned long long carry = 0ull, key = 0ull;
+    int32_t ne = -1;
+    for (int c0 = 0; c0 < a.n_hb; c0 += 64) {
+      const int f = c0 + lane;
+      const unsigned long long k = f < a.n_hb ? rk[f] : kUnpublished;
+      const bool pub = k != kUnpublished;
+      unsigned long long v = pub ? k : 0ull;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long u = __shfl_up(v, o);
+        if (lane >= o) v = max(v, u);
       }
+      v = max(v, carry);
+      const uint32_t m = min(static_cast<uint32_t>(f + 1) * static_cast<uint32_t>(kRoundHyps),
+                             n_hyp);
+      const bool stop = f < a.n_hb && pub &&
+                        (m >= n_hyp || enough_samples(key_count(v), n, m, a.one_minus_conf));
+      const uint64_t sb = __ballot(stop), ub = __ballot(f < a.n_hb && !pub);
+      if (sb != 0ull) {
+        const int fs = __ffsll(static_cast<long long>(sb)) - 1;   // first round where it holds
+        // a round before it unpublished cannot happen (reported as -1)
+        const bool gap = (ub & ((2ull << fs) - 1ull)) != 0ull;
+        const unsigned long long vk = __shfl(v, fs);
+        key = vk;
+        ne = gap ? -1 : static_cast<int32_t>(min(static_cast<uint32_t>(c0 + fs + 1) *
+                                                     static_cast<uint32_t>(kRoundHyps),
+                                                 n_hyp));
+        break;
+      }
+      if (ub != 0ull) break;   // unpublished before any stop: -1
+      carry = __shfl(v, 63);
+    }
+    if (lane == 0) {
+      skey = key;
+      sne = ne;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long key;
+    int32_t ne;
+    if (a.pst) {
+      key = skey;
+      ne = sne;
     } else {
       key = a.keys[p];
+      ne = a.n_hyp;
     }
     if (a.n_eval) a.n_eval[p] = ne;
     if (key != 0ull) {

@@ -360,10 +360,16 @@ def bench_ransac_batched(stream):
     br = hgpu.BatchedRansac(corr, off, nh, 3.0, 3)
     tune = br.autotune(cb.off)
     g = br.graph(tune)
-    t, p = time_launches(g.launch, 20, 3, stream)
-    ms_graph = float(np.median(p))
-    t, p = time_launches(lambda: br.run(tune), 20, 3, stream)
-    ms_direct = float(np.median(p))
+    # graph replays and direct launches interleaved, so that both see the same clock state
+    pg, pd = [], []
+    for _ in range(3):
+        g.launch()
+        br.run(tune)
+    for _ in range(20):
+        pg += time_launches(g.launch, 1, 0, stream)[1]
+        pd += time_launches(lambda: br.run(tune), 1, 0, stream)[1]
+    ms_graph = float(np.median(pg))
+    ms_direct = float(np.median(pd))
     g.close()
     # plain per-problem form: one fused single-pair call per pair, host loop
     total = corr.shape[1]

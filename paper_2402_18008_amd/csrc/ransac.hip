@@ -406,7 +406,9 @@ __global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
 // published round keys in order, as a sequential loop would (a round before
 // the stopping point is always published; if one were missing, n_evaluated
 // would read -1).
-__global__ __launch_bounds__(kThreads) void ransac_finish_kernel(RansacArgs a) {
+constexpr int kFinishThreads = 1024;
+
+__global__ __launch_bounds__(kFinishThreads) void ransac_finish_kernel(RansacArgs a) {
   __shared__ float bestH[9];
   __shared__ unsigned long long skey;
   __shared__ int32_t sne;
@@ -491,9 +493,25 @@ __global__ __launch_bounds__(kThreads) void ransac_finish_kernel(RansacArgs a) {
   score_form(bestH, a.inv_tau, hh);
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
-  for (uint32_t i = threadIdx.x; i < n; i += kThreads)
-    a.mask[base + i] =
-        (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
+  // 4 points per thread in flight (indices clamped into the pair for the loads)
+  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4u * kFinishThreads) {
+    float x1[4], y1[4], x2[4], y2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t j = min(i0 + static_cast<uint32_t>(u) * kFinishThreads, n - 1u);
+      x1[u] = X1[j];
+      y1[u] = Y1[j];
+      x2[u] = X2[j];
+      y2[u] = Y2[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + static_cast<uint32_t>(u) * kFinishThreads;
+      if (i < n)
+        a.mask[base + i] =
+            (any && inlier(hh, x1[u], y1[u], x2[u] * a.inv_tau, y2[u] * a.inv_tau)) ? 1 : 0;
+    }
+  }
 }
 
 // Single pair, after the fused kernel: reduce the work items' best keys (every
@@ -910,8 +928,8 @@ static int launch_batched(const RansacArgs &a0, const hg_ransac_tuning &t, void 
                                            std::max<int64_t>(1, a.n_items));
   hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, a);
   if (int st = launched("ransac_kernel<persistent>")) return st;
-  hipLaunchKernelGGL(ransac_finish_kernel, dim3(static_cast<unsigned>(a.n_pairs)), dim3(kThreads),
-                     0, s, a);
+  hipLaunchKernelGGL(ransac_finish_kernel, dim3(static_cast<unsigned>(a.n_pairs)),
+                     dim3(kFinishThreads), 0, s, a);
   return launched("ransac_finish_kernel");
 }
 

@@ -167,8 +167,9 @@ int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
  * Pair p owns points [off[p], off[p+1]) of the concatenated planes (corr at
  * stride ld >= off[n_pairs]); every pair runs n_hyp hypotheses with Philox
  * counter (j, p, 0, 0). One persistent kernel drains a queue of (pair,
- * hypothesis block) items, largest pairs first; the last block to finish a
- * pair writes its mask. Per pair, the arithmetic is that of hg_ransac (same
+ * hypothesis block) items, largest pairs first, each folding its best key
+ * into the pair's; a finish kernel then writes every pair's best outputs and
+ * mask. Per pair, the arithmetic is that of hg_ransac (same
  * device functions) with Philox counter word 1 = p; results do not depend
  * on the tuning.
  *   off         n_pairs + 1 int64 (device); every pair needs >= 4 points.
@@ -200,10 +201,11 @@ int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t
  * pair of N_p points; large pairs' rounds spread through the queue) when
  * n_pairs^2 * rounds <= 2^27, else round-major. Rounds past a pair's stopping
  * point (or past the bound that the best count so far gives) are skipped, or
- * abandoned once a wave sees it (checked every 8 hypotheses), and are never
- * merged, so results do not depend on order or timing. Same arguments as
- * hg_ransac_batched otherwise (no per-hypothesis
- * counts); 0 < confidence < 1; tune->hyps_per_block is ignored (64).
+ * abandoned once a wave sees it (checked every 8 hypotheses); the finish
+ * kernel applies the rule to the published round keys in order, so results
+ * do not depend on order or timing. Same arguments as hg_ransac_batched
+ * otherwise (no per-hypothesis counts); 0 < confidence < 1;
+ * tune->hyps_per_block is ignored (64).
  * ws >= hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max) bytes.               */
 size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max);
 int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,

@@ -297,7 +297,7 @@ int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t
  * hg_warp_l1_bwd recomputes everything from H (nothing per pixel is stored)
  * and writes grad_H (B x 9 doubles) = grad_loss[b] * dloss[b]/dH_b, with
  * d|r|/dr = sign(r) (0 at 0) and the floor treated as constant.
- * Errors: B < 0, h or w outside [1, 32768], NULL pointer with B > 0 ->
+ * Errors: B < 0, h or w outside [1, 32768], h w > 2^29, NULL pointer with B > 0 ->
  * HG_EINVAL; B == 0 is a no-op.                                             */
 int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t B, int32_t h,
                    int32_t w, float *loss, void *stream);
@@ -313,7 +313,7 @@ int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const fl
  *   hg_photometric_fwd: loss (B floats).
  *   hg_photometric_bwd: grad_offsets (B x 4 x 2 floats) = grad_loss[b] *
  *     dloss[b]/d offsets_b.
- * Errors: B < 0, h or w outside [2, 32768], NULL pointer with B > 0 ->
+ * Errors: B < 0, h or w outside [2, 32768], h w > 2^29, NULL pointer with B > 0 ->
  * HG_EINVAL; B == 0 is a no-op.                                            */
 int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt, int32_t B,
                        int32_t h, int32_t w, float *loss, void *stream);
@@ -332,7 +332,7 @@ int hg_photometric_bwd(const float *offsets, const float *img, const float *tgt,
  * hg_refine launches on the stream; hg_refine_graph_create captures the same
  * sequence (with these pointers and scalars) for hg_graph_launch (allocates,
  * synchronises; needs B > 0).
- * Errors: B < 0, h or w outside [2, 32768], iters outside [0, 1000],
+ * Errors: B < 0, h or w outside [2, 32768], h w > 2^29, iters outside [0, 1000],
  * non-finite step, NULL img/tgt/offsets with B > 0 -> HG_EINVAL. B == 0 is a
  * no-op.                                                                   */
 int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w, int32_t iters,

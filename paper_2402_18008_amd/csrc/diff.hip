@@ -188,15 +188,24 @@ __device__ __forceinline__ int adjugate_scaled(const double *Hd, double G[9]) {
   return e;
 }
 
-// Bilinear sampling with zero padding, split into an address stage (all four
-// taps clamped into the image, so every load is in bounds) and an evaluation
-// stage, so that a thread can issue the loads of several pixels before using
-// any of them.
+// Bilinear sampling with zero padding, split into an address stage and an
+// evaluation stage, so that a thread can issue the loads of several pixels
+// before using any of them. The patch image is read as a raw buffer of its
+// h w floats, whose loads return 0 at byte offsets past its end (the hardware's
+// range check): a row above the image gets an offset past the end, a row below
+// it lies past the end already, and the two tap columns are clamped into the
+// image and masked. Offsets are 32-bit and never negative.
+constexpr uint32_t kFarOffset = 0x80000000u;   // past every patch (h w <= 2^29 floats)
+
 struct TapAddr {
-  int i00, i01, i10, i11;   // clamped linear indices
-  uint32_t in;              // bit k set when tap k lies inside the image
-  double ax, ay;            // fractional position in the cell
+  uint32_t o00, o01, o10, o11;   // byte offsets of taps (x0, y0), (x1, y0), (x0, y1), (x1, y1)
+  bool x0in, x1in;               // tap columns inside the image
+  double ax, ay;                 // fractional position in the cell
 };
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_buffer(const float *I, int P) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(I), 0, P * 4, 0x00020000);
+}
 
 __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
   if (!(fabs(sx) < 1.0e6) || !(fabs(sy) < 1.0e6)) {   // far outside or nan: all taps outside
@@ -208,17 +217,31 @@ __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) 
   t.ax = sx - fx;
   t.ay = sy - fy;
   const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
-  const bool x0in = ix >= 0 && ix < w, x1in = ix + 1 >= 0 && ix + 1 < w;
-  const bool y0in = iy >= 0 && iy < h, y1in = iy + 1 >= 0 && iy + 1 < h;
-  const int cx0 = min(max(ix, 0), w - 1), cx1 = min(max(ix + 1, 0), w - 1);
-  const int cy0 = min(max(iy, 0), h - 1), cy1 = min(max(iy + 1, 0), h - 1);
-  t.i00 = cy0 * w + cx0;
-  t.i01 = cy0 * w + cx1;
-  t.i10 = cy1 * w + cx0;
-  t.i11 = cy1 * w + cx1;
-  t.in = (y0in && x0in ? 1u : 0u) | (y0in && x1in ? 2u : 0u) | (y1in && x0in ? 4u : 0u) |
-         (y1in && x1in ? 8u : 0u);
+  // cells with a tap inside the image; any other cell has all four taps outside
+  const bool near = ix >= -1 && ix < w && iy >= -1 && iy < h;
+  const uint32_t row0 = near && iy >= 0 ? static_cast<uint32_t>(iy * w) * 4u : kFarOffset;
+  const uint32_t row1 = near ? static_cast<uint32_t>((iy + 1) * w) * 4u : kFarOffset;
+  const uint32_t c0 = static_cast<uint32_t>(max(ix, 0)) * 4u;
+  const uint32_t c1 = static_cast<uint32_t>(min(ix + 1, w - 1)) * 4u;
+  t.o00 = row0 + c0;
+  t.o01 = row0 + c1;
+  t.o10 = row1 + c0;
+  t.o11 = row1 + c1;
+  t.x0in = ix >= 0;
+  t.x1in = ix + 1 < w;
   return t;
+}
+
+// The four taps of a cell (column-masked; rows outside read 0).
+__device__ __forceinline__ void tap_load(__amdgpu_buffer_rsrc_t r, const TapAddr &t, float L[4]) {
+  const float v00 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o00, 0, 0));
+  const float v01 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o01, 0, 0));
+  const float v10 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o10, 0, 0));
+  const float v11 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o11, 0, 0));
+  L[0] = t.x0in ? v00 : 0.0f;
+  L[1] = t.x1in ? v01 : 0.0f;
+  L[2] = t.x0in ? v10 : 0.0f;
+  L[3] = t.x1in ? v11 : 0.0f;
 }
 
 struct Tap {
@@ -228,10 +251,8 @@ struct Tap {
 template <bool GRAD>
 __device__ __forceinline__ Tap tap_eval(const TapAddr &a, float L00, float L01, float L10,
                                         float L11) {
-  const double I00 = (a.in & 1u) ? static_cast<double>(L00) : 0.0;
-  const double I01 = (a.in & 2u) ? static_cast<double>(L01) : 0.0;
-  const double I10 = (a.in & 4u) ? static_cast<double>(L10) : 0.0;
-  const double I11 = (a.in & 8u) ? static_cast<double>(L11) : 0.0;
+  const double I00 = static_cast<double>(L00), I01 = static_cast<double>(L01);
+  const double I10 = static_cast<double>(L10), I11 = static_cast<double>(L11);
   const double top = fma(a.ax, I01 - I00, I00);
   const double bot = fma(a.ax, I11 - I10, I10);
   Tap t;
@@ -360,7 +381,7 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
   int e;
   load_G(Hb, G, e);
   const int P = h * w;
-  const float *I = img + static_cast<int64_t>(b) * P;
+  const __amdgpu_buffer_rsrc_t rs = patch_buffer(img + static_cast<int64_t>(b) * P, P);
   const float *T = (MODE == 0) ? tgt + static_cast<int64_t>(b) * P : nullptr;
   double acc[1] = {0.0};
   PixelWalk pw(w);
@@ -372,10 +393,7 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
       double sx, sy, iq2;
       sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx, sy, iq2);
       ta[u] = tap_addr(sx, sy, h, w);
-      L[u][0] = I[ta[u].i00];
-      L[u][1] = I[ta[u].i01];
-      L[u][2] = I[ta[u].i10];
-      L[u][3] = I[ta[u].i11];
+      tap_load(rs, ta[u], L[u]);
       const int i = min(i0 + u * kDiffThreads, P - 1);
       if (MODE == 0) tv[u] = T[i];
     }
@@ -441,7 +459,7 @@ __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__
   int e;
   load_G(Hb, G, e);
   const int P = h * w;
-  const float *I = img + static_cast<int64_t>(b) * P;
+  const __amdgpu_buffer_rsrc_t rs = patch_buffer(img + static_cast<int64_t>(b) * P, P);
   const float *T = FROM_STORED ? grad_warped + static_cast<int64_t>(b) * P
                                : tgt + static_cast<int64_t>(b) * P;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -455,10 +473,7 @@ __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__
       sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx[u], sy[u],
                  iq2[u]);
       ta[u] = tap_addr(sx[u], sy[u], h, w);
-      L[u][0] = I[ta[u].i00];
-      L[u][1] = I[ta[u].i01];
-      L[u][2] = I[ta[u].i10];
-      L[u][3] = I[ta[u].i11];
+      tap_load(rs, ta[u], L[u]);
       tv[u] = T[min(i0 + u * kDiffThreads, P - 1)];
     }
 #pragma unroll
@@ -585,8 +600,9 @@ __global__ void l1_bwd_kernel(const float *__restrict__ warped, const float *__r
 
 static int check_img(const void *a, const void *b2, int B, int h, int w, const char *fn) {
   HG_REQUIRE(B >= 0, "%s: B < 0", fn);
-  HG_REQUIRE(h >= 1 && w >= 1 && h <= 32768 && w <= 32768, "%s: image size %d x %d out of range",
-             fn, h, w);
+  HG_REQUIRE(h >= 1 && w >= 1 && h <= 32768 && w <= 32768 &&
+                 static_cast<int64_t>(h) * w <= (int64_t(1) << 29),
+             "%s: image size %d x %d out of range", fn, h, w);
   if (B == 0) return HG_OK;
   HG_REQUIRE(a && b2, "%s: NULL pointer", fn);
   return HG_OK;
@@ -675,8 +691,9 @@ static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h,
                        int32_t iters, float step, float *offsets, float *loss, const char *fn,
                        RefineArgs &a) {
   HG_REQUIRE(B >= 0, "%s: B < 0", fn);
-  HG_REQUIRE(h >= 2 && w >= 2 && h <= 32768 && w <= 32768, "%s: image size %d x %d out of range",
-             fn, h, w);
+  HG_REQUIRE(h >= 2 && w >= 2 && h <= 32768 && w <= 32768 &&
+                 static_cast<int64_t>(h) * w <= (int64_t(1) << 29),
+             "%s: image size %d x %d out of range", fn, h, w);
   HG_REQUIRE(iters >= 0 && iters <= 1000, "%s: iters = %d outside [0, 1000]", fn, iters);
   HG_REQUIRE(std::isfinite(step), "%s: step is not finite", fn);
   if (B > 0) HG_REQUIRE(img && tgt && offsets, "%s: NULL img, tgt or offsets", fn);

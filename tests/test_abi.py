@@ -200,6 +200,10 @@ def test_diff_validation(lib):
     assert lib.hg_warp_l1_fwd(FAKE, None, FAKE, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
     assert lib.hg_warp_l1_fwd(None, FAKE, FAKE, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
     assert lib.hg_warp_l1_fwd(None, None, None, 0, 128, 128, None, None) == _abi.HG_OK
+    # at most 2^29 pixels per patch (32-bit byte offsets into the patch)
+    assert lib.hg_warp_l1_fwd(None, None, None, 0, 32768, 32768, None, None) == _abi.HG_EINVAL
+    assert lib.hg_warp_l1_fwd(None, None, None, 0, 16384, 32768, None, None) == _abi.HG_OK
+    assert lib.hg_photometric_fwd(None, None, None, 0, 32768, 32768, None, None) == _abi.HG_EINVAL
     assert lib.hg_warp_l1_bwd(FAKE, FAKE, FAKE, None, 4, 128, 128, FAKE, None) == _abi.HG_EINVAL
     assert lib.hg_warp_store_fwd(FAKE, FAKE, 4, 128, 40000, FAKE, None) == _abi.HG_EINVAL
     assert lib.hg_l1_fwd(FAKE, FAKE, 4, 128, 128, None, None) == _abi.HG_EINVAL

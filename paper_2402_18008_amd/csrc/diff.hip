@@ -382,7 +382,9 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
   load_G(Hb, G, e);
   const int P = h * w;
   const __amdgpu_buffer_rsrc_t rs = patch_buffer(img + static_cast<int64_t>(b) * P, P);
-  const float *T = (MODE == 0) ? tgt + static_cast<int64_t>(b) * P : nullptr;
+  // the target as a buffer too: indices past the patch (the last loop's tail) read 0
+  const __amdgpu_buffer_rsrc_t rt = patch_buffer(MODE == 0 ? tgt + static_cast<int64_t>(b) * P
+                                                           : img, P);
   double acc[1] = {0.0};
   PixelWalk pw(w);
   for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
@@ -394,8 +396,9 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
       sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx, sy, iq2);
       ta[u] = tap_addr(sx, sy, h, w);
       tap_load(rs, ta[u], L[u]);
-      const int i = min(i0 + u * kDiffThreads, P - 1);
-      if (MODE == 0) tv[u] = T[i];
+      if (MODE == 0)
+        tv[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rt, static_cast<uint32_t>(i0 + u * kDiffThreads) * 4u, 0, 0));
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {

@@ -8,7 +8,9 @@
 // move pixels across the kinks of the bilinear and L1 terms and change the
 // gradient by ~1e-3 relative. One 256-thread workgroup per patch; per-patch
 // sums are accumulated per thread and across the workgroup in double.
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "solver_dev.hpp"
@@ -269,18 +271,19 @@ __device__ __forceinline__ Tap tap_eval(const TapAddr &a, float L00, float L01, 
 // Pixels per thread per loop iteration (loads of all of them in flight at once).
 constexpr int kUnroll = 4;
 
-// Per-thread pixel walker: pixel i = threadIdx.x + u * kDiffThreads + k *
-// kDiffThreads * kUnroll, with (x, y) advanced incrementally.
+// Per-thread pixel walker (NT threads): pixel i = threadIdx.x + u * NT + k *
+// NT * kUnroll, with (x, y) advanced incrementally.
+template <int NT>
 struct PixelWalk {
   int x[kUnroll], y[kUnroll];
   int step_x, step_y, w;
   __device__ __forceinline__ PixelWalk(int w_) : w(w_) {
-    constexpr int kStep = kDiffThreads * kUnroll;
+    constexpr int kStep = NT * kUnroll;
     step_y = kStep / w;
     step_x = kStep % w;
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int i = static_cast<int>(threadIdx.x) + u * kDiffThreads;
+      const int i = static_cast<int>(threadIdx.x) + u * NT;
       y[u] = i / w;
       x[u] = i % w;
     }
@@ -298,11 +301,11 @@ struct PixelWalk {
   }
 };
 
-// Workgroup sum of NV per-thread float partials, in double. Result valid in
+// Workgroup (NT threads) sum of NV per-thread partials, in double. Result valid in
 // thread 0.
-template <int NV>
+template <int NV, int NT>
 __device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[NV]) {
-  __shared__ double red[kDiffThreads / 64][NV];
+  __shared__ double red[NT / 64][NV];
   double s[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -319,7 +322,7 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[N
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double t = 0.0;
-      for (int q = 0; q < kDiffThreads / 64; ++q) t += red[q][k];
+      for (int q = 0; q < NT / 64; ++q) t += red[q][k];
       out[k] = t;
     }
   }
@@ -372,7 +375,7 @@ __device__ __forceinline__ void sample_pos(const double *G, double x, double y, 
 
 // One patch b per workgroup; Hb: its 9 entries of H (global or LDS).
 // MODE 0: loss only; 2: stored warp only (rounded to float).
-template <int MODE>
+template <int MODE, int NT>
 __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__restrict__ img,
                                                const float *__restrict__ tgt, int h, int w, int b,
                                                float *__restrict__ loss,
@@ -386,8 +389,8 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
   const __amdgpu_buffer_rsrc_t rt = patch_buffer(MODE == 0 ? tgt + static_cast<int64_t>(b) * P
                                                            : img, P);
   double acc[1] = {0.0};
-  PixelWalk pw(w);
-  for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
+  PixelWalk<NT> pw(w);
+  for (int i0 = threadIdx.x; i0 < P; i0 += NT * kUnroll) {
     TapAddr ta[kUnroll];
     float L[kUnroll][4], tv[kUnroll];
 #pragma unroll
@@ -398,11 +401,11 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
       tap_load(rs, ta[u], L[u]);
       if (MODE == 0)
         tv[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-            rt, static_cast<uint32_t>(i0 + u * kDiffThreads) * 4u, 0, 0));
+            rt, static_cast<uint32_t>(i0 + u * NT) * 4u, 0, 0));
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int i = i0 + u * kDiffThreads;
+      const int i = i0 + u * NT;
       if (i < P) {
         const double v = tap_eval<false>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]).v;
         if (MODE == 2) warped[static_cast<int64_t>(b) * P + i] = static_cast<float>(v);
@@ -413,19 +416,19 @@ __device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__
   }
   if (MODE == 0) {
     double s[1];
-    block_sum<1>(acc, s);
+    block_sum<1, NT>(acc, s);
     if (threadIdx.x == 0) loss[b] = static_cast<float>(s[0] / static_cast<double>(P));
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kDiffThreads) void warp_fwd_kernel(const double *__restrict__ H,
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void warp_fwd_kernel(const double *__restrict__ H,
                                                                 const float *__restrict__ img,
                                                                 const float *__restrict__ tgt,
                                                                 int h, int w,
                                                                 float *__restrict__ loss,
                                                                 float *__restrict__ warped) {
-  warp_fwd_block<MODE>(H + 9 * blockIdx.x, img, tgt, h, w, blockIdx.x, loss, warped);
+  warp_fwd_block<MODE, NT>(H + 9 * blockIdx.x, img, tgt, h, w, blockIdx.x, loss, warped);
 }
 
 // dL/dH from dL/dG (G = 2^-e adj(H)), thread 0, double precision.
@@ -453,7 +456,7 @@ __device__ __forceinline__ void adjugate_backward(const double *Hd, const double
 // writes dL/dH to gHout (9 doubles).
 // FROM_STORED = false: recompute r = I_w - T and use sign(r) gl, gl = grad_loss / (h w);
 // FROM_STORED = true: read dL/dI_w from grad_warped.
-template <bool FROM_STORED>
+template <bool FROM_STORED, int NT>
 __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__restrict__ img,
                                                const float *__restrict__ tgt, double gl,
                                                const float *__restrict__ grad_warped, int h,
@@ -466,8 +469,8 @@ __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__
   const float *T = FROM_STORED ? grad_warped + static_cast<int64_t>(b) * P
                                : tgt + static_cast<int64_t>(b) * P;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  PixelWalk pw(w);
-  for (int i0 = threadIdx.x; i0 < P; i0 += kDiffThreads * kUnroll) {
+  PixelWalk<NT> pw(w);
+  for (int i0 = threadIdx.x; i0 < P; i0 += NT * kUnroll) {
     TapAddr ta[kUnroll];
     double sx[kUnroll], sy[kUnroll], iq2[kUnroll];
     float L[kUnroll][4], tv[kUnroll];
@@ -477,11 +480,11 @@ __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__
                  iq2[u]);
       ta[u] = tap_addr(sx[u], sy[u], h, w);
       tap_load(rs, ta[u], L[u]);
-      tv[u] = T[min(i0 + u * kDiffThreads, P - 1)];
+      tv[u] = T[min(i0 + u * NT, P - 1)];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (i0 + u * kDiffThreads >= P) continue;
+      if (i0 + u * NT >= P) continue;
       const Tap t = tap_eval<true>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]);
       double g;
       if (FROM_STORED) {
@@ -507,19 +510,19 @@ __device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__
     pw.advance();
   }
   double gG[9];
-  block_sum<9>(acc, gG);
+  block_sum<9, NT>(acc, gG);
   if (threadIdx.x == 0) adjugate_backward(Hb, gG, e, gHout);
 }
 
-template <bool FROM_STORED>
-__global__ __launch_bounds__(kDiffThreads) void warp_bwd_kernel(
+template <bool FROM_STORED, int NT>
+__global__ __launch_bounds__(NT) void warp_bwd_kernel(
     const double *__restrict__ H, const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ grad_loss, const float *__restrict__ grad_warped, int h, int w,
     double *__restrict__ grad_H) {
   const int b = blockIdx.x;
   const double gl =
       FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(h * w);
-  warp_bwd_block<FROM_STORED>(H + 9 * b, img, tgt, gl, grad_warped, h, w, b, grad_H + 9 * b);
+  warp_bwd_block<FROM_STORED, NT>(H + 9 * b, img, tgt, gl, grad_warped, h, w, b, grad_H + 9 * b);
 }
 
 // ---- fused offsets -> loss and offsets -> gradient (one workgroup per patch) --
@@ -540,20 +543,21 @@ __device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kDiffThreads) void photo_fwd_kernel(const float *__restrict__ off,
+template <int NT>
+__global__ __launch_bounds__(NT) void photo_fwd_kernel(const float *__restrict__ off,
                                                                  const float *__restrict__ img,
                                                                  const float *__restrict__ tgt,
                                                                  int h, int w, RectArgs ra,
                                                                  float *__restrict__ loss) {
   __shared__ double Hs[9];
   rect_to_lds(off + 8 * blockIdx.x, ra, Hs);
-  warp_fwd_block<0>(Hs, img, tgt, h, w, blockIdx.x, loss, nullptr);
+  warp_fwd_block<0, NT>(Hs, img, tgt, h, w, blockIdx.x, loss, nullptr);
 }
 
 // grad_offsets = grad_loss[b] dL_b/d offsets_b; with STEP, instead
 // offsets_b -= step * float(dL_b/d offsets_b) in place (grad_loss = 1).
-template <bool STEP>
-__global__ __launch_bounds__(kDiffThreads) void photo_bwd_kernel(
+template <bool STEP, int NT>
+__global__ __launch_bounds__(NT) void photo_bwd_kernel(
     float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ grad_loss, int h, int w, RectArgs ra, float step,
     float *__restrict__ goff) {
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(kDiffThreads) void photo_bwd_kernel(
   const int b = blockIdx.x;
   rect_to_lds(off + 8 * b, ra, Hs);
   const double gl = static_cast<double>(STEP ? 1.0f : grad_loss[b]) / static_cast<double>(h * w);
-  warp_bwd_block<false>(Hs, img, tgt, gl, nullptr, h, w, b, gHs);
+  warp_bwd_block<false, NT>(Hs, img, tgt, gl, nullptr, h, w, b, gHs);
   if (threadIdx.x == 0) {
     double g[8];
     rect_bwd_one(off + 8 * b, gHs, ra.x0, ra.y0, ra.w, ra.r, g);
@@ -585,7 +589,7 @@ __global__ void l1_fwd_kernel(const float *__restrict__ warped, const float *__r
   for (int64_t i = threadIdx.x; i < P; i += kDiffThreads)
     acc[0] += fabs(static_cast<double>(warped[b * P + i]) - static_cast<double>(tgt[b * P + i]));
   double s[1];
-  block_sum<1>(acc, s);
+  block_sum<1, kDiffThreads>(acc, s);
   if (threadIdx.x == 0) loss[b] = static_cast<float>(s[0] / static_cast<double>(P));
 }
 
@@ -675,16 +679,48 @@ static RectArgs patch_rect(int h, int w) {
   return ra;
 }
 
+// Threads per patch workgroup: enough for about 4096 waves in flight over the
+// batch (16 per CU), from 256 threads at B >= 1024 up to MAXNT (1024 for the
+// forward kernels; 512 for the backward ones, which would spill registers at
+// 1024).
+static int diff_threads(int B, int max_nt) {
+  const int64_t want = (int64_t(4096) * 64 + B - 1) / std::max(B, 1);
+  const int nt = want <= 256 ? 256 : want <= 512 ? 512 : 1024;
+  return std::min(nt, max_nt);
+}
+
+template <int MAXNT = 1024, typename F>
+static void with_threads(int B, F &&f) {
+  const int nt = diff_threads(B, MAXNT);
+  if constexpr (MAXNT >= 1024) {
+    if (nt == 1024) {
+      f(std::integral_constant<int, 1024>());
+      return;
+    }
+  }
+  if (nt == 512) {
+    f(std::integral_constant<int, 512>());
+    return;
+  }
+  f(std::integral_constant<int, 256>());
+}
+
 static int launch_refine(const RefineArgs &a, hipStream_t s) {
   const RectArgs ra = patch_rect(a.h, a.w);
   for (int it = 0; it < a.iters; ++it) {
-    hipLaunchKernelGGL(photo_bwd_kernel<true>, dim3(a.B), dim3(kDiffThreads), 0, s, a.off, a.img,
-                       a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
+    with_threads<512>(a.B, [&](auto nt) {
+      constexpr int NT = decltype(nt)::value;
+      hipLaunchKernelGGL((photo_bwd_kernel<true, NT>), dim3(a.B), dim3(NT), 0, s, a.off, a.img,
+                         a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
+    });
     if (int st = launched("photo_bwd_kernel<step>")) return st;
   }
   if (a.loss) {
-    hipLaunchKernelGGL(photo_fwd_kernel, dim3(a.B), dim3(kDiffThreads), 0, s, a.off, a.img, a.tgt,
-                       a.h, a.w, ra, a.loss);
+    with_threads(a.B, [&](auto nt) {
+      constexpr int NT = decltype(nt)::value;
+      hipLaunchKernelGGL((photo_fwd_kernel<NT>), dim3(a.B), dim3(NT), 0, s, a.off, a.img, a.tgt,
+                         a.h, a.w, ra, a.loss);
+    });
     if (int st = launched("photo_fwd_kernel")) return st;
   }
   return HG_OK;
@@ -778,8 +814,11 @@ extern "C" int hg_warp_l1_fwd(const double *H, const float *img, const float *tg
   if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_fwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && loss, "hg_warp_l1_fwd: NULL pointer");
-  hipLaunchKernelGGL(warp_fwd_kernel<0>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H, img,
-                     tgt, h, w, loss, nullptr);
+  with_threads(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((warp_fwd_kernel<0, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H, img,
+                       tgt, h, w, loss, nullptr);
+  });
   return launched("warp_fwd_kernel");
 }
 
@@ -790,8 +829,11 @@ extern "C" int hg_warp_l1_bwd(const double *H, const float *img, const float *tg
   if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_bwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_loss && grad_H, "hg_warp_l1_bwd: NULL pointer");
-  hipLaunchKernelGGL(warp_bwd_kernel<false>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H,
-                     img, tgt, grad_loss, nullptr, h, w, grad_H);
+  with_threads<512>(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((warp_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
+                       img, tgt, grad_loss, nullptr, h, w, grad_H);
+  });
   return launched("warp_bwd_kernel");
 }
 
@@ -801,8 +843,11 @@ extern "C" int hg_warp_store_fwd(const double *H, const float *img, int32_t B, i
   if (int st = check_img(img, warped, B, h, w, "hg_warp_store_fwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H, "hg_warp_store_fwd: NULL H");
-  hipLaunchKernelGGL(warp_fwd_kernel<2>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H, img,
-                     nullptr, h, w, nullptr, warped);
+  with_threads(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((warp_fwd_kernel<2, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H, img,
+                       nullptr, h, w, nullptr, warped);
+  });
   return launched("warp_fwd_kernel<store>");
 }
 
@@ -835,8 +880,11 @@ extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const fl
   if (int st = check_img(img, grad_warped, B, h, w, "hg_warp_bwd_from_grad")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_H, "hg_warp_bwd_from_grad: NULL pointer");
-  hipLaunchKernelGGL(warp_bwd_kernel<true>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), H,
-                     img, nullptr, nullptr, grad_warped, h, w, grad_H);
+  with_threads<512>(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((warp_bwd_kernel<true, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
+                       img, nullptr, nullptr, grad_warped, h, w, grad_H);
+  });
   return launched("warp_bwd_kernel<stored>");
 }
 
@@ -847,8 +895,11 @@ extern "C" int hg_photometric_fwd(const float *offsets, const float *img, const 
   HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_fwd: patches need h, w >= 2");
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && loss, "hg_photometric_fwd: NULL offsets or loss");
-  hipLaunchKernelGGL(photo_fwd_kernel, dim3(B), dim3(kDiffThreads), 0, as_stream(stream), offsets,
-                     img, tgt, h, w, patch_rect(h, w), loss);
+  with_threads(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((photo_fwd_kernel<NT>), dim3(B), dim3(NT), 0, as_stream(stream), offsets,
+                       img, tgt, h, w, patch_rect(h, w), loss);
+  });
   return launched("photo_fwd_kernel");
 }
 
@@ -860,9 +911,12 @@ extern "C" int hg_photometric_bwd(const float *offsets, const float *img, const 
   HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_bwd: patches need h, w >= 2");
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && grad_loss && grad_offsets, "hg_photometric_bwd: NULL pointer");
-  hipLaunchKernelGGL(photo_bwd_kernel<false>, dim3(B), dim3(kDiffThreads), 0, as_stream(stream),
-                     const_cast<float *>(offsets), img, tgt, grad_loss, h, w, patch_rect(h, w), 0.0f,
-                     grad_offsets);
+  with_threads<512>(B, [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((photo_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream),
+                       const_cast<float *>(offsets), img, tgt, grad_loss, h, w, patch_rect(h, w),
+                       0.0f, grad_offsets);
+  });
   return launched("photo_bwd_kernel");
 }
 

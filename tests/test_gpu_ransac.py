@@ -346,6 +346,36 @@ def test_adaptive_equal_and_odd_ratio_sizes():
         check_adaptive_pair(corr[:, a:b], 1000, 29, p, got, f"equal-size pair {p}")
 
 
+def test_adaptive_config3_sampled():
+    """Adaptive termination on the 512-pair workload in the benchmark's launch
+    shape (16 points per lane, 4 workgroups per CU): sampled pairs against the
+    oracle's sequential rule, invariants on every pair."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    cb = synth.config3()
+    announce("adaptive config3 512 pairs, cap 1024")
+    ar = hgpu.AdaptiveRansac(torch.from_numpy(cb.corr).cuda(), torch.from_numpy(cb.off).cuda(),
+                             1024, TAU, 3, confidence=0.99)
+    ar.run((16, 64, 4))
+    torch.cuda.synchronize()
+    out = dict(best_H=ar.best_H.cpu().numpy(), best_count=ar.best_count.cpu().numpy(),
+               best_hyp=ar.best_hyp.cpu().numpy(), n_eval=ar.n_evaluated.cpu().numpy(),
+               mask=ar.mask.cpu().numpy())
+    ne = out["n_eval"]
+    assert np.all((ne % 64 == 0) | (ne == 1024)) and ne.min() >= 64 and ne.max() <= 1024
+    for p in range(512):
+        a, b = cb.off[p], cb.off[p + 1]
+        assert int(out["mask"][a:b].sum()) == int(out["best_count"][p]), p
+    ns = np.diff(cb.off)
+    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), int(np.argmax(ne)), int(np.argmin(ne)),
+                   0, 101, 257, 400})
+    for p in pick:
+        a, b = cb.off[p], cb.off[p + 1]
+        got = dict(best_H=out["best_H"][p], best_count=out["best_count"][p],
+                   best_hyp=out["best_hyp"][p], n_eval=ne[p], mask=out["mask"][a:b])
+        check_adaptive_pair(cb.corr[:, a:b], 1024, 3, p, got, f"adaptive config3 pair {p}")
+
+
 def test_batched_rejects_bad_offsets():
     """Offsets are checked on the host before any launch: decreasing, out of
     range, or a pair with fewer than 4 points is refused."""

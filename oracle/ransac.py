@@ -74,9 +74,11 @@ def decision_band(H, corr, tau):
     inlier iff ru'^2 + rv'^2 <= w^2 -- in exact arithmetic the same test as
     ||pi(H x1) - x2|| <= tau. The H entries may also be one float32 ulp off.
 
-    Each 3-term dot product (two fused or separate roundings, one-ulp
-    perturbation of every H entry, the rounding of c h) errs by at most 4u
-    times the sum of the magnitudes of its terms (u = 2^-24); the residual
+    Each 3-term dot product errs by at most 5u times the sum of the
+    magnitudes of its terms (u = 2^-24): 3u for its evaluation, whether as two
+    fused multiply-adds or with every product and partial sum rounded (as a
+    matrix unit's dot product may be), u for a one-ulp perturbation of every
+    H entry and u for the rounding of c h; the residual
     adds one rounding and the rounding of c x2 (u |x2 w| each). Propagating to
     e = ru^2 + rv^2 - tau^2 w^2 (three more roundings on each square) bounds
     the error of e; since e = w^2 (dist - tau)(dist + tau), the decision can
@@ -95,9 +97,9 @@ def decision_band(H, corr, tau):
     w = Hs[:, 2, 0, None] * x1 + Hs[:, 2, 1, None] * y1 + Hs[:, 2, 2, None]
     ru = u - x2 * w
     rv = v - y2 * w
-    Ew = 4 * U32 * Sw
-    Eru = 4 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + 2 * ax2 * np.abs(w))
-    Erv = 4 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + 2 * ay2 * np.abs(w))
+    Ew = 5 * U32 * Sw
+    Eru = 5 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + 2 * ax2 * np.abs(w))
+    Erv = 5 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + 2 * ay2 * np.abs(w))
     d = ru * ru + rv * rv
     t = tau * tau * w * w
     Ee = (2 * np.abs(ru) * Eru + Eru ** 2 + 2 * np.abs(rv) * Erv + Erv ** 2 + 3 * U32 * d

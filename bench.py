@@ -108,6 +108,49 @@ def write_traffic(fetch_dir, write_dir, n):
     print(json.dumps(out, indent=1))
 
 
+def burst_us(fn, stream, launches=200, warmup=10):
+    """Per-launch time of `launches` back-to-back eager calls under one event pair
+    (host launch cost included where it exceeds the kernel's)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / launches
+
+
+def graph_us(fn, stream, per_graph=100, replays=10):
+    """Per-launch time of fn() replayed from a captured graph of `per_graph`
+    back-to-back calls (no host launch cost)."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per_graph):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(replays):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (per_graph * replays)
+    del g
+    return us
+
+
 def time_launches(fn, steps, warmup, stream):
     """Run fn() warmup times, then time `steps` calls with one event pair each.
     Returns (total_ms, per_launch_ms list)."""
@@ -627,6 +670,17 @@ def main():
                                  reps, 10, stream)
             us = float(np.median(p)) * 1e3
             sweep[str(m)] = {"us_per_launch": us, "homographies_per_s": m / (us * 1e-6)}
+            if m <= 1000000:
+                # averaged over back-to-back launches, as the paper's table is: eager, and
+                # replayed from a graph (checked against the eager result)
+                ref = hm_.clone()
+                hm_.zero_()
+                gus = graph_us(lambda: hgpu.hg_solve4(sm_, dm_, hgpu.HG_ACA, H=hm_, flags=fm_),
+                               stream)
+                assert torch.equal(hm_, ref), f"graph-replayed solve differs at n = {m}"
+                bus = burst_us(lambda: hgpu.hg_solve4(sm_, dm_, hgpu.HG_ACA, H=hm_, flags=fm_),
+                               stream)
+                sweep[str(m)].update(us_per_launch_burst=bus, us_per_launch_graph=gus)
         extra["aca_batch_size_sweep"] = sweep
         # small batch latency: 4096 quadruples
         for meth, name in ((hgpu.HG_ACA, "aca"), (hgpu.HG_SKS, "sks")):

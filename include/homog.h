@@ -173,6 +173,8 @@ int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
  * device functions) with Philox counter word 1 = p; results do not depend
  * on the tuning.
  *   off         n_pairs + 1 int64 (device); every pair needs >= 4 points.
+ *   n_pairs * ceil(n_hyp / 16) <= 2^31 (the work queue's counter is 32-bit;
+ *               HG_EINVAL beyond).
  *   best_H      n_pairs x 9 floats; best_count, best_hyp n_pairs int32;
  *   inlier_mask off[n_pairs] bytes; hyp_counts n_pairs x n_hyp or NULL.
  *   tune        launch shape, NULL = the cached autotuned or default choice.

@@ -942,6 +942,13 @@ static int check_batched(const float *corr, int64_t ld, const int64_t *off, int3
   HG_REQUIRE(n_pairs >= 1, "hg_ransac_batched: n_pairs = %d < 1", n_pairs);
   HG_REQUIRE(ld >= 1, "hg_ransac_batched: ld < 1");
   HG_REQUIRE(n_hyp >= 1, "hg_ransac_batched: n_hyp = %d < 1", n_hyp);
+  // the persistent queue is a 32-bit counter that every workgroup also bumps
+  // once past the end: at most 2^31 work items (of >= 16 hypotheses) keep it
+  // from wrapping, which would restart the queue and never end the launch
+  HG_REQUIRE(static_cast<int64_t>(n_pairs) * ((static_cast<int64_t>(n_hyp) + 15) / 16) <=
+                 (int64_t(1) << 31),
+             "hg_ransac_batched: n_pairs x n_hyp too large for one launch (n_pairs * "
+             "ceil(n_hyp / 16) must be <= 2^31)");
   HG_REQUIRE(std::isfinite(thresh) && thresh > 0.0f && std::isfinite(1.0f / thresh),
              "hg_ransac_batched: threshold must be finite and > 0 (and 1/threshold finite)");
   HG_REQUIRE(!tune || tune_valid(*tune), "hg_ransac_batched: unsupported tuning");

@@ -175,6 +175,9 @@ def test_batched_validation(lib):
     assert call(th=-1.0) == _abi.HG_EINVAL
     assert call(bh=None) == _abi.HG_EINVAL
     assert call(wsb=need - 1) == _abi.HG_EWORKSPACE
+    # more than 2^31 work items would wrap the persistent queue's 32-bit counter
+    assert call(n_hyp=2**31 - 1) == _abi.HG_EINVAL
+    assert b"too large" in lib.hg_last_error()
     bad = _abi.Tuning(5, 16, 1, 0)
     assert call(tune=C.byref(bad)) == _abi.HG_EINVAL
     bad = _abi.Tuning(8, 48, 1, 0)
@@ -244,3 +247,5 @@ def test_adaptive_validation(lib):
     assert call(n_pairs=0) == _abi.HG_EINVAL
     assert call(th=0.0) == _abi.HG_EINVAL
     assert call(wsb=need - 1) == _abi.HG_EWORKSPACE
+    assert lib.hg_ransac_adaptive(FAKE, 10, FAKE, 2**20, 2**20, 3.0, 1, 0.99, None, FAKE, FAKE, FAKE,
+                                  FAKE, FAKE, ws, need, None) == _abi.HG_EINVAL

@@ -151,6 +151,28 @@ def graph_us(fn, stream, per_graph=100, replays=10):
     return us
 
 
+def time_interleaved(fns, rounds, warmup, stream):
+    """Per-call times (ms) of several forms queued alternately (order reversed every other
+    round) without synchronising in between: the host stays ahead, each interval is the GPU's
+    time for one call, and every form sees the same clock state."""
+    import torch
+    for _ in range(warmup):
+        for f in fns.values():
+            f()
+    torch.cuda.synchronize()
+    keys = list(fns)
+    evs = {k: [] for k in keys}
+    for r in range(rounds):
+        for k in (keys if r % 2 == 0 else keys[::-1]):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fns[k]()
+            b.record(stream)
+            evs[k].append((a, b))
+    torch.cuda.synchronize()
+    return {k: [a.elapsed_time(b) for a, b in v] for k, v in evs.items()}
+
+
 def time_launches(fn, steps, warmup, stream):
     """Run fn() warmup times, then time `steps` calls with one event pair each.
     Returns (total_ms, per_launch_ms list)."""
@@ -504,12 +526,10 @@ def bench_diff(stream):
         hgpu.hg_photometric_fwd(off, imgs[k], tgts[k])
         hgpu.hg_photometric_bwd(off, imgs[k], tgts[k], gl)
 
-    t, p = time_launches(fused, 40, 4, stream)
-    ms_f = float(np.median(p))
-    t, p = time_launches(recompute, 40, 4, stream)
-    ms_r = float(np.median(p))
-    t, p = time_launches(stored, 40, 4, stream)
-    ms_s = float(np.median(p))
+    ts = time_interleaved({"fused": fused, "recompute": recompute, "stored": stored}, 40, 4, stream)
+    ms_f = float(np.median(ts["fused"]))
+    ms_r = float(np.median(ts["recompute"]))
+    ms_s = float(np.median(ts["stored"]))
     min_bytes = 2 * B * S * S * 4          # img and tgt read once
     out = {"warp_l1_1024x128x128": {
         "fused_ms": ms_f, "recompute_ms": ms_r, "stored_ms": ms_s,

@@ -679,19 +679,19 @@ static RectArgs patch_rect(int h, int w) {
   return ra;
 }
 
-// Threads per patch workgroup: enough for about 4096 waves in flight over the
-// batch (16 per CU), from 256 threads at B >= 1024 up to MAXNT (1024 for the
-// forward kernels; 512 for the backward ones, which would spill registers at
-// 1024).
-static int diff_threads(int B, int max_nt) {
-  const int64_t want = (int64_t(4096) * 64 + B - 1) / std::max(B, 1);
+// Threads per patch workgroup: enough for about WAVES waves in flight over the
+// batch, from 256 threads up to MAXNT. The forward kernels aim at 8192 waves
+// (32 per CU) with up to 1024 threads; the backward ones at 4096 with up to
+// 512 (they would spill registers at 1024, and more waves did not help them).
+static int diff_threads(int B, int max_nt, int waves) {
+  const int64_t want = (int64_t(waves) * 64 + B - 1) / std::max(B, 1);
   const int nt = want <= 256 ? 256 : want <= 512 ? 512 : 1024;
   return std::min(nt, max_nt);
 }
 
-template <int MAXNT = 1024, typename F>
+template <int MAXNT = 1024, int WAVES = 8192, typename F>
 static void with_threads(int B, F &&f) {
-  const int nt = diff_threads(B, MAXNT);
+  const int nt = diff_threads(B, MAXNT, WAVES);
   if constexpr (MAXNT >= 1024) {
     if (nt == 1024) {
       f(std::integral_constant<int, 1024>());
@@ -708,7 +708,7 @@ static void with_threads(int B, F &&f) {
 static int launch_refine(const RefineArgs &a, hipStream_t s) {
   const RectArgs ra = patch_rect(a.h, a.w);
   for (int it = 0; it < a.iters; ++it) {
-    with_threads<512>(a.B, [&](auto nt) {
+    with_threads<512, 4096>(a.B, [&](auto nt) {
       constexpr int NT = decltype(nt)::value;
       hipLaunchKernelGGL((photo_bwd_kernel<true, NT>), dim3(a.B), dim3(NT), 0, s, a.off, a.img,
                          a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
@@ -829,7 +829,7 @@ extern "C" int hg_warp_l1_bwd(const double *H, const float *img, const float *tg
   if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_bwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_loss && grad_H, "hg_warp_l1_bwd: NULL pointer");
-  with_threads<512>(B, [&](auto nt) {
+  with_threads<512, 4096>(B, [&](auto nt) {
     constexpr int NT = decltype(nt)::value;
     hipLaunchKernelGGL((warp_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
                        img, tgt, grad_loss, nullptr, h, w, grad_H);
@@ -880,7 +880,7 @@ extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const fl
   if (int st = check_img(img, grad_warped, B, h, w, "hg_warp_bwd_from_grad")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_H, "hg_warp_bwd_from_grad: NULL pointer");
-  with_threads<512>(B, [&](auto nt) {
+  with_threads<512, 4096>(B, [&](auto nt) {
     constexpr int NT = decltype(nt)::value;
     hipLaunchKernelGGL((warp_bwd_kernel<true, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
                        img, nullptr, nullptr, grad_warped, h, w, grad_H);
@@ -911,7 +911,7 @@ extern "C" int hg_photometric_bwd(const float *offsets, const float *img, const 
   HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_bwd: patches need h, w >= 2");
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && grad_loss && grad_offsets, "hg_photometric_bwd: NULL pointer");
-  with_threads<512>(B, [&](auto nt) {
+  with_threads<512, 4096>(B, [&](auto nt) {
     constexpr int NT = decltype(nt)::value;
     hipLaunchKernelGGL((photo_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream),
                        const_cast<float *>(offsets), img, tgt, grad_loss, h, w, patch_rect(h, w),

@@ -53,31 +53,51 @@ __device__ __forceinline__ void load_batch(const float *X1, const float *Y1, con
   }
 }
 
-// Workgroup sum of NV doubles; the result is valid in thread 0.
+// Sum of a double over each row of 16 lanes, in the row's last lane: an
+// inclusive scan by DPP row shifts of its two 32-bit halves (lanes shifted in
+// from outside the row read 0). No LDS round trips, unlike shuffles.
+__device__ __forceinline__ double row_sum16_f64(double x) {
+#define HG_ROW_SHR(N)                                                              \
+  {                                                                                \
+    const int lo = __double2loint(x), hi = __double2hiint(x);                      \
+    const int slo = __builtin_amdgcn_update_dpp(0, lo, 0x110 + N, 0xF, 0xF, false); \
+    const int shi = __builtin_amdgcn_update_dpp(0, hi, 0x110 + N, 0xF, 0xF, false); \
+    x += __hiloint2double(shi, slo);                                               \
+  }
+  HG_ROW_SHR(1)
+  HG_ROW_SHR(2)
+  HG_ROW_SHR(4)
+  HG_ROW_SHR(8)
+#undef HG_ROW_SHR
+  return x;
+}
+
+// Workgroup sum of NV doubles; the result is valid in thread 0. Each row of 16
+// lanes sums its values (row_sum16_f64), then thread k adds the rows' partials
+// of value k in row order: a fixed order, so the result is deterministic.
 template <int NV>
 __device__ __forceinline__ void refit_block_sum(double (&v)[NV]) {
-  __shared__ double red[kRefitThreads / 64][NV];
+  constexpr int kRows = kRefitThreads / 16;
+  static_assert(NV <= kRefitThreads, "one thread per value");
+  __shared__ double red[NV][kRows];
+  __shared__ double tot[NV];
+  const int t = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[k] = x;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[wv][k] = v[k];
+    const double s = row_sum16_f64(v[k]);
+    if ((t & 15) == 15) red[k][t >> 4] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t < NV) {
+    double s = red[t][0];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = red[0][k];
+    for (int r = 1; r < kRows; ++r) s += red[t][r];
+    tot[t] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
 #pragma unroll
-      for (int w = 1; w < kRefitThreads / 64; ++w) s += red[w][k];
-      v[k] = s;
-    }
+    for (int k = 0; k < NV; ++k) v[k] = tot[k];
   }
   __syncthreads();
 }
@@ -162,10 +182,15 @@ __host__ __device__ inline void smallest_eigvec3(double A[3][3], double v[3]) {
     }
   }
   int m = 0;
-  if (A[1][1] < A[m][m]) m = 1;
-  if (A[2][2] < A[m][m]) m = 2;
+  double am = A[0][0];
+  if (A[1][1] < am) {
+    m = 1;
+    am = A[1][1];
+  }
+  if (A[2][2] < am) m = 2;
+  // selects rather than a variable index, which would put V in scratch memory
 #pragma unroll
-  for (int k = 0; k < 3; ++k) v[k] = V[k][m];
+  for (int k = 0; k < 3; ++k) v[k] = m == 0 ? V[k][0] : (m == 1 ? V[k][1] : V[k][2]);
 }
 
 // Eigenvector of the smallest eigenvalue of a symmetric positive

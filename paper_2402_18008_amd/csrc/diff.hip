@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "lanes.hpp"
 #include "solver_dev.hpp"
 
 namespace hg {
@@ -302,29 +303,31 @@ struct PixelWalk {
 };
 
 // Workgroup (NT threads) sum of NV per-thread partials, in double. Result valid in
-// thread 0.
+// thread 0. Each row of 16 lanes sums its values (row_sum16_f64), then thread k
+// adds the rows' partials of value k in row order: a fixed order, so the result
+// is deterministic.
 template <int NV, int NT>
 __device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[NV]) {
-  __shared__ double red[NT / 64][NV];
-  double s[NV];
+  constexpr int kRows = NT / 16;
+  static_assert(NV <= NT, "one thread per value");
+  __shared__ double red[NV][kRows];
+  __shared__ double tot[NV];
+  const int t = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    s[k] = v[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_down(s[k], o);
+    const double r = row_sum16_f64(v[k]);
+    if ((t & 15) == 15) red[k][t >> 4] = r;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[wave][k] = s[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t < NV) {
+    double x = red[t][0];
+    for (int q = 1; q < kRows; ++q) x += red[t][q];
+    tot[t] = x;
+  }
+  __syncthreads();
+  if (t == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double t = 0.0;
-      for (int q = 0; q < NT / 64; ++q) t += red[q][k];
-      out[k] = t;
-    }
+    for (int k = 0; k < NV; ++k) out[k] = tot[k];
   }
 }
 

@@ -207,7 +207,8 @@ int hg_ransac_batched(const float *corr, int64_t ld, const int64_t *off, int32_t
  * kernel applies the rule to the published round keys in order, so results
  * do not depend on order or timing. Same arguments as hg_ransac_batched
  * otherwise (no per-hypothesis counts); 0 < confidence < 1;
- * tune->hyps_per_block is ignored (64).
+ * tune->hyps_per_block is ignored (64); with tune NULL the cached batched
+ * choice is used with at most 4 blocks per compute unit.
  * ws >= hg_ransac_adaptive_ws_bytes(n_pairs, n_hyp_max) bytes.               */
 size_t hg_ransac_adaptive_ws_bytes(int32_t n_pairs, int32_t n_hyp_max);
 int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
@@ -238,8 +239,10 @@ int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *off, int32_
 int hg_refit_ho(const float *corr, int64_t ld, const int64_t *off, int32_t n_pairs,
                 const uint8_t *mask, float *H, int32_t *n_used, uint8_t *flags, void *stream);
 
-/* Times every supported tuning on the given problem (allocates temporary
- * outputs, synchronises the stream) and stores the fastest in *out and in the
+/* Times the tunings {8, 16} points per lane x {16, 32, 64} hypotheses per
+ * block x {1, 2, 4, 5, 6} blocks per compute unit on the given problem (7 and
+ * 8 blocks per unit do not fit in the registers at once); allocates temporary
+ * outputs and synchronises the stream. Stores the fastest in *out and in the
  * process-wide cache used when tune == NULL; also written to the JSON file
  * named by HG_AUTOTUNE_CACHE if that variable is set. off_host mirrors off. */
 int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *off,

@@ -748,7 +748,7 @@ static bool tune_valid(const hg_ransac_tuning &t) {
          t.blocks_per_cu >= 1 && t.blocks_per_cu <= 8;
 }
 
-static const hg_ransac_tuning kDefaultTune = {16, 32, 2, 0};
+static const hg_ransac_tuning kDefaultTune = {16, 64, 4, 0};
 
 typedef void (*KernelFn)(RansacArgs);
 
@@ -1100,7 +1100,7 @@ extern "C" int hg_ransac_autotune(const float *corr, int64_t ld, const int64_t *
   int status = HG_OK;
   for (int P : {8, 16})
     for (int HB : {16, 32, 64})
-      for (int bpc : {1, 2, 4}) {
+      for (int bpc : {1, 2, 4, 5, 6}) {
         const hg_ransac_tuning t = {P, HB, bpc, 0};
         RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp, HB, thresh, seed, bh, bc, bi,
                                  mk, nullptr);
@@ -1174,6 +1174,9 @@ extern "C" int hg_ransac_adaptive(const float *corr, int64_t ld, const int64_t *
                 need, ws_bytes);
   hg_ransac_tuning t = tune ? *tune : lookup_tune(n_pairs, n_hyp_max);
   t.hyps_per_block = kRound;   // a work item is one round
+  // without an explicit shape: at most 4 workgroups per CU (more rounds in
+  // flight at once means more speculative rounds past the stopping points)
+  if (!tune) t.blocks_per_cu = std::min(t.blocks_per_cu, 4);
   RansacArgs a = make_args(corr, ld, off, 0, n_pairs, n_hyp_max, kRound, thresh, seed, best_H,
                            best_count, best_hyp, inlier_mask, nullptr);
   char *x = static_cast<char *>(ws) + batched_ws_bytes(n_pairs);

@@ -167,7 +167,7 @@ def test_batched_small_all_tunings_identical():
     ref = None
     for P in (8, 16):
         for HB in (16, 32, 64):
-            for bpc in (1, 2, 4):
+            for bpc in (1, 2, 4, 5, 6):
                 announce(f"batched 24 pairs tuning P={P} HB={HB} bpc={bpc}")
                 br.run((P, HB, bpc))
                 out = np_out(br)

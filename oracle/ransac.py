@@ -15,9 +15,12 @@ What is computed (the paper's RANSAC stage: sample 4 correspondences, solve the
   the inliers of the best H (no refit); with no valid hypothesis best = -1.
 
 The verification here is evaluated in float64 with a division and a square
-root, i.e. by the definition. ``decision_band`` bounds how far a float32
-division-free evaluation of the same test may stray, which is the tolerance
-under which counts from such an evaluation are compared.
+root, i.e. by the definition. Counts are compared exactly except for points
+whose transfer error lies within ``band_px`` (1e-4 px) of the threshold, where
+any two correct evaluations may disagree (``count_lo`` / ``count_hi``).
+``decision_band`` is a diagnostic: it bounds how far a float32 division-free
+evaluation of the same test may stray, i.e. how wide the exemption would have
+to be for a scorer that decides in float32 alone.
 """
 from __future__ import annotations
 
@@ -74,11 +77,9 @@ def decision_band(H, corr, tau):
     inlier iff ru'^2 + rv'^2 <= w^2 -- in exact arithmetic the same test as
     ||pi(H x1) - x2|| <= tau. The H entries may also be one float32 ulp off.
 
-    Each 3-term dot product errs by at most 5u times the sum of the
-    magnitudes of its terms (u = 2^-24): 3u for its evaluation, whether as two
-    fused multiply-adds or with every product and partial sum rounded (as a
-    matrix unit's dot product may be), u for a one-ulp perturbation of every
-    H entry and u for the rounding of c h; the residual
+    Each 3-term dot product (two fused or separate roundings, one-ulp
+    perturbation of every H entry, the rounding of c h) errs by at most 4u
+    times the sum of the magnitudes of its terms (u = 2^-24); the residual
     adds one rounding and the rounding of c x2 (u |x2 w| each). Propagating to
     e = ru^2 + rv^2 - tau^2 w^2 (three more roundings on each square) bounds
     the error of e; since e = w^2 (dist - tau)(dist + tau), the decision can
@@ -97,9 +98,9 @@ def decision_band(H, corr, tau):
     w = Hs[:, 2, 0, None] * x1 + Hs[:, 2, 1, None] * y1 + Hs[:, 2, 2, None]
     ru = u - x2 * w
     rv = v - y2 * w
-    Ew = 5 * U32 * Sw
-    Eru = 5 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + 2 * ax2 * np.abs(w))
-    Erv = 5 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + 2 * ay2 * np.abs(w))
+    Ew = 4 * U32 * Sw
+    Eru = 4 * U32 * Su + ax2 * Ew + U32 * (np.abs(u) + 2 * ax2 * np.abs(w))
+    Erv = 4 * U32 * Sv + ay2 * Ew + U32 * (np.abs(v) + 2 * ay2 * np.abs(w))
     d = ru * ru + rv * rv
     t = tau * tau * w * w
     Ee = (2 * np.abs(ru) * Eru + Eru ** 2 + 2 * np.abs(rv) * Erv + Erv ** 2 + 3 * U32 * d
@@ -113,9 +114,10 @@ def decision_band(H, corr, tau):
 def ransac_ref(corr, n_hyp, tau, seed, pair=0, band_px=1e-4, chunk=512):
     """Full single-pair reference. Returns a dict with idx, H32, flags, valid,
     counts (int64, 0 for invalid), count_lo / count_hi (counts with every point
-    inside the decision band taken as outlier / inlier), best_hyp, best_count,
-    best_H (float32), mask (uint8) and mask_exempt (bool: mask entries inside
-    the band)."""
+    whose transfer error is within band_px of tau taken as outlier / inlier),
+    n_exempt (per hypothesis, the number of such points), best_hyp,
+    best_count, best_H (float32), mask (uint8) and mask_exempt (bool: mask
+    entries within band_px of tau)."""
     corr = np.asarray(corr, np.float32)
     idx, H32, flags, valid = hypotheses(corr, n_hyp, seed, pair)
     counts = np.zeros(n_hyp, np.int64)
@@ -124,22 +126,20 @@ def ransac_ref(corr, n_hyp, tau, seed, pair=0, band_px=1e-4, chunk=512):
     for a in range(0, n_hyp, chunk):
         b = min(n_hyp, a + chunk)
         d = transfer_error(H32[a:b], corr)
-        band = np.maximum(decision_band(H32[a:b], corr, tau), band_px)
         inl = d <= tau
-        ex = np.abs(d - tau) <= band
+        ex = np.abs(d - tau) < band_px
         v = valid[a:b, None]
         counts[a:b] = (inl & v).sum(axis=1)
         lo[a:b] = (inl & ~ex & v).sum(axis=1)
         hi[a:b] = ((inl | ex) & v).sum(axis=1)
     out = dict(idx=idx, H32=H32, flags=flags, valid=valid, counts=counts,
-               count_lo=lo, count_hi=hi)
+               count_lo=lo, count_hi=hi, n_exempt=hi - lo)
     if valid.any():
         c = np.where(valid, counts, -1)
         best = int(np.argmax(c))            # first maximum = lowest index
         d = transfer_error(H32[best:best + 1], corr)[0]
-        band = np.maximum(decision_band(H32[best:best + 1], corr, tau)[0], band_px)
         out.update(best_hyp=best, best_count=int(counts[best]), best_H=H32[best].copy(),
-                   mask=(d <= tau).astype(np.uint8), mask_exempt=np.abs(d - tau) <= band)
+                   mask=(d <= tau).astype(np.uint8), mask_exempt=np.abs(d - tau) < band_px)
     else:
         n = corr.shape[1]
         out.update(best_hyp=-1, best_count=0, best_H=np.zeros((3, 3), np.float32),
@@ -180,16 +180,11 @@ def required_iterations(eps, conf=0.99):
     return math.ceil(math.log(1.0 - conf) / math.log1p(-eps ** 4))
 
 
-def ransac_adaptive_ref(corr, n_hyp_max, tau, seed, pair=0, conf=0.99, round_size=64,
-                        band_px=1e-4):
-    """Adaptive single-pair reference. Hypotheses are evaluated in rounds of
-    ``round_size`` (in index order); after each round the best so far gives
-    eps = best_count / N, and the loop stops once the number evaluated m
-    reaches min(required_iterations(eps), n_hyp_max). Returns the ransac_ref
-    dict restricted to the evaluated prefix plus n_eval."""
-    full = ransac_ref(corr, n_hyp_max, tau, seed, pair=pair, band_px=band_px)
-    n = np.asarray(corr).shape[1]
-    valid, counts = full["valid"], full["counts"]
+def stopping_point(valid, counts, n, n_hyp_max, conf=0.99, round_size=64):
+    """Hypotheses evaluated by the sequential adaptive loop: rounds of
+    ``round_size`` in index order; after each round eps = best count so far / n,
+    and the loop ends once the number evaluated m reaches
+    min(required_iterations(eps), n_hyp_max)."""
     m = 0
     for r in range((n_hyp_max + round_size - 1) // round_size):
         m = min((r + 1) * round_size, n_hyp_max)
@@ -197,16 +192,35 @@ def ransac_adaptive_ref(corr, n_hyp_max, tau, seed, pair=0, conf=0.99, round_siz
         best_count = int(c.max()) if valid[:m].any() else 0
         if m >= min(required_iterations(best_count / n, conf), n_hyp_max):
             break
+    return m
+
+
+def ransac_adaptive_ref(corr, n_hyp_max, tau, seed, pair=0, conf=0.99, round_size=64,
+                        band_px=1e-4):
+    """Adaptive single-pair reference. Hypotheses are evaluated in rounds of
+    ``round_size`` (in index order); after each round the best so far gives
+    eps = best_count / N, and the loop stops once the number evaluated m
+    reaches min(required_iterations(eps), n_hyp_max). Returns the ransac_ref
+    dict restricted to the evaluated prefix plus n_eval, and n_eval_min /
+    n_eval_max: the stopping points when every exempt point is taken as an
+    inlier / an outlier."""
+    full = ransac_ref(corr, n_hyp_max, tau, seed, pair=pair, band_px=band_px)
+    n = np.asarray(corr).shape[1]
+    valid, counts = full["valid"], full["counts"]
+    m = stopping_point(valid, counts, n, n_hyp_max, conf, round_size)
     out = dict(full)
     out["n_eval"] = m
+    # the rule stops no later when counts are larger: bounds on the stopping
+    # point over every choice of the exempt points' decisions
+    out["n_eval_min"] = stopping_point(valid, full["count_hi"], n, n_hyp_max, conf, round_size)
+    out["n_eval_max"] = stopping_point(valid, full["count_lo"], n, n_hyp_max, conf, round_size)
     v = valid[:m]
     if v.any():
         c = np.where(v, counts[:m], -1)
         best = int(np.argmax(c))
         d = transfer_error(full["H32"][best:best + 1], corr)[0]
-        bandv = np.maximum(decision_band(full["H32"][best:best + 1], corr, tau)[0], band_px)
         out.update(best_hyp=best, best_count=int(counts[best]), best_H=full["H32"][best].copy(),
-                   mask=(d <= tau).astype(np.uint8), mask_exempt=np.abs(d - tau) <= bandv)
+                   mask=(d <= tau).astype(np.uint8), mask_exempt=np.abs(d - tau) < band_px)
     else:
         out.update(best_hyp=-1, best_count=0, best_H=np.zeros((3, 3), np.float32),
                    mask=np.zeros(n, np.uint8), mask_exempt=np.zeros(n, bool))

@@ -2,12 +2,14 @@
 
 Bar (integer results): the sampled hypotheses' validity is exact (up to
 samples whose minimum triangle height lies within a relative 1e-3 of the
-degeneracy threshold); every per-hypothesis count lies in the oracle's
-[count_lo, count_hi], i.e. it equals the float64 count except for points whose
-transfer error is within the float32 decision band of the threshold; the
-winning H matches the oracle's within 1e-5 (it is the same float64 ACA, scaled
-and rounded); the mask equals the oracle's inlier set of that H outside the
-band; fused, plain and persistent forms agree bit for bit."""
+degeneracy threshold); every per-hypothesis count equals the oracle's float64
+count except for points whose transfer error lies within 1e-4 px of the
+threshold (it lies in the oracle's [count_lo, count_hi] at that band); the
+best hypothesis is the lowest-index maximum of the GPU counts and equals the
+oracle's wherever no exempt point can change the order; the winning H matches
+the oracle's within 1e-5 (it is the same float64 ACA, scaled and rounded);
+the mask equals the oracle's inlier set of that H outside the 1e-4 px band;
+fused, plain and persistent forms agree bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -19,6 +21,7 @@ from tests.gpu_util import announce, require_gpu
 
 pytestmark = pytest.mark.gpu
 TAU = 3.0
+BAND_PX = 1e-4      # counts are exact except points this close to the threshold
 
 
 def to_np(d):
@@ -42,7 +45,16 @@ def check_pair(corr, n_hyp, seed, got, pair=0, label=""):
     ok = valid_o & nb
     lo, hi = ref["count_lo"], ref["count_hi"]
     bad = ok & ((counts < lo) | (counts > hi))
-    assert not bad.any(), (label, np.nonzero(bad)[0][:8], counts[bad][:8], lo[bad][:8], hi[bad][:8])
+    if bad.any():
+        j = np.nonzero(bad)[0][:8]
+        # diagnostic: how far the mis-counted points lie from the threshold,
+        # next to the float32 decision band of those hypotheses
+        d = oref.transfer_error(ref["H32"][j], corr)
+        band = oref.decision_band(ref["H32"][j], corr, TAU)
+        near = np.abs(d - TAU)
+        k = np.argsort(near, axis=1)[:, :3]
+        raise AssertionError((label, j, counts[j], ref["counts"][j], lo[j], hi[j],
+                              np.take_along_axis(near, k, 1), np.take_along_axis(band, k, 1)))
     # argmax over the GPU counts, ties to the lowest index
     bh = int(got["best_hyp"].reshape(-1)[0])
     bc = int(got["best_count"].reshape(-1)[0])
@@ -57,8 +69,7 @@ def check_pair(corr, n_hyp, seed, got, pair=0, label=""):
     assert hg.herr(Hg, ref["H32"][bh].astype(np.float64)) <= 1e-5, label
     # mask: the inliers of that H, outside the decision band
     d = oref.transfer_error(ref["H32"][bh:bh + 1], corr)[0]
-    band = np.maximum(oref.decision_band(ref["H32"][bh:bh + 1], corr, TAU)[0], 1e-4)
-    ex = np.abs(d - TAU) <= band
+    ex = np.abs(d - TAU) < BAND_PX
     m = got["mask"].astype(bool)
     assert np.array_equal(m[~ex], (d <= TAU)[~ex]), label
     assert int(m.sum()) == bc
@@ -232,13 +243,19 @@ def test_config3_persistent_graph_and_autotune():
 # ---- adaptive termination ------------------------------------------------------
 
 def check_adaptive_pair(corr, n_hyp_max, seed, pair, got, label):
-    ref = oref.ransac_adaptive_ref(corr, n_hyp_max, TAU, seed, pair=pair)
+    """The GPU's stopping point lies between the sequential rule's stopping
+    points with every exempt point an inlier and with every one an outlier
+    (the rule is monotone in the best count), and equals it where those agree;
+    the winner is the oracle's wherever no exempt point can change it."""
+    ref = oref.ransac_adaptive_ref(corr, n_hyp_max, TAU, seed, pair=pair, band_px=BAND_PX)
     m_gpu = int(got["n_eval"])
     m_ref = ref["n_eval"]
-    valid, lo, hi = ref["valid"], ref["count_lo"], ref["count_hi"]
-    exact = bool((lo[valid] == hi[valid]).all())
-    if exact:
+    assert ref["n_eval_min"] <= m_gpu <= ref["n_eval_max"], (label, m_gpu, ref["n_eval_min"],
+                                                              ref["n_eval_max"])
+    if ref["n_eval_min"] == ref["n_eval_max"]:
         assert m_gpu == m_ref, (label, m_gpu, m_ref)
+    valid, lo, hi = ref["valid"], ref["count_lo"], ref["count_hi"]
+    exact = bool((lo[:m_gpu][valid[:m_gpu]] == hi[:m_gpu][valid[:m_gpu]]).all())
     assert m_gpu % 64 == 0 or m_gpu == n_hyp_max, label
     bh, bc = int(got["best_hyp"]), int(got["best_count"])
     v = valid[:m_gpu]
@@ -253,8 +270,7 @@ def check_adaptive_pair(corr, n_hyp_max, seed, pair, got, label):
     Hg = got["best_H"].reshape(3, 3)
     assert hg.herr(Hg, ref["H32"][bh].astype(np.float64)) <= 1e-5, label
     d = oref.transfer_error(ref["H32"][bh:bh + 1], corr)[0]
-    band = np.maximum(oref.decision_band(ref["H32"][bh:bh + 1], corr, TAU)[0], 1e-4)
-    ex = np.abs(d - TAU) <= band
+    ex = np.abs(d - TAU) < BAND_PX
     mk = got["mask"].astype(bool)
     assert np.array_equal(mk[~ex], (d <= TAU)[~ex]), label
     assert int(mk.sum()) == bc

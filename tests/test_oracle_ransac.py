@@ -121,7 +121,7 @@ def test_decision_band_covers_float32_evaluation(fused, case):
         assert np.all(np.abs(d - tau)[mis] <= band[mis])
         n_band += (np.abs(d - tau) <= np.maximum(band, 1e-4)).sum()
     # the band is narrow: a handful of the 8.2M (hypothesis, point) pairs
-    assert n_band < 150
+    assert n_band < 100
 
 
 def test_config2_planted_model_found():

@@ -67,7 +67,7 @@ def _apply(H, x, y):
     return u, v, w
 
 
-def _quad_chunk(seed, chunk, m, degenerate_every, base_index):
+def _quad_chunk(seed, chunk, m, degenerate_every, base_index, with_h=False):
     rng = np.random.default_rng([seed, chunk])
     x = rng.uniform(0.0, FRAME_W, (m, 4))
     y = rng.uniform(0.0, FRAME_H, (m, 4))
@@ -114,6 +114,8 @@ def _quad_chunk(seed, chunk, m, degenerate_every, base_index):
     src[1::2] = y.T
     dst[0::2] = xd.T
     dst[1::2] = yd.T
+    if with_h:
+        return src, dst, labels, H
     return src, dst, labels
 
 
@@ -144,6 +146,13 @@ def quadruples(n, seed, degenerate_every=0, chunks=None):
         dst[:, lo:lo + m] = d
         lab[lo:lo + m] = l
     return src, dst, lab
+
+
+def quadruple_chunk(seed, chunk, degenerate_every=0, m=CHUNK, with_h=False):
+    """Chunk ``chunk`` (quadruples chunk*CHUNK ... + m) of ``quadruples(n, seed,
+    degenerate_every)`` alone, without drawing the others; with ``with_h`` also
+    the ground-truth homographies (m, 3, 3) drawn for it."""
+    return _quad_chunk(seed, chunk, m, degenerate_every, chunk * CHUNK, with_h)
 
 
 def _quad_worker(args):

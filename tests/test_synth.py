@@ -54,3 +54,116 @@ def test_pattern_images():
     assert abs(np.median(cx) - 320) < 15 and abs(np.median(cy) - 240) < 15
     span = np.hypot(d1[2] - d1[0], d1[3] - d1[1])          # image of the M N edge (160 units)
     assert 0.4 * 160 < np.median(span) < 2.5 * 160
+
+
+# ---- distributions of the drawn parameters (KS / chi-square pins) ------------
+
+from scipy import stats  # noqa: E402
+
+P_MIN = 1e-4   # fixed seeds: each statistic is a fixed number; this is far below typical p-values
+
+
+def _uniform_p(x, lo, hi):
+    return stats.kstest(np.asarray(x, np.float64), "uniform", args=(lo, hi - lo)).pvalue
+
+
+def _similarity_params(H):
+    s = np.hypot(H[:, 0, 0], H[:, 1, 0])
+    th = np.arctan2(H[:, 1, 0], H[:, 0, 0])
+    return s, th, H[:, 0, 2], H[:, 1, 2], H[:, 2, 0], H[:, 2, 1]
+
+
+def test_similarity_perspective_draws():
+    """Scale U[0.5, 2], rotation U[-pi, pi], translation U[-100, 100]^2,
+    perspective U[-1e-3, 1e-3]^2, h33 = 1, and the rotation block orthogonal."""
+    H = synth._random_similarity_persp(np.random.default_rng(123), 100000)
+    s, th, tx, ty, p, q = _similarity_params(H)
+    assert np.allclose(H[:, 0, 0], H[:, 1, 1]) and np.allclose(H[:, 0, 1], -H[:, 1, 0])
+    assert np.all(H[:, 2, 2] == 1.0)
+    for x, lo, hi in ((s, 0.5, 2.0), (th, -np.pi, np.pi), (tx, -100, 100), (ty, -100, 100),
+                      (p, -1e-3, 1e-3), (q, -1e-3, 1e-3)):
+        assert x.min() >= lo and x.max() <= hi
+        assert _uniform_p(x, lo, hi) > P_MIN
+
+
+def test_quadruple_chunk_distributions():
+    """Source points uniform in the frame; every point has w >= 0.1 after the
+    perspective redraw (which changes few draws); target noise N(0, 0.5^2);
+    planted near-degenerate sets have a triangle of height <= 1e-3 px."""
+    src, dst, lab, H = synth.quadruple_chunk(1, 0, degenerate_every=100, m=50000, with_h=True)
+    s, th, tx, ty, p, q = _similarity_params(H)
+    for x, lo, hi in ((s, 0.5, 2.0), (th, -np.pi, np.pi), (tx, -100, 100)):
+        assert _uniform_p(x, lo, hi) > P_MIN
+    ok = lab == 0
+    assert _uniform_p(src[0::2][:, ok].ravel(), 0, 640) > P_MIN
+    assert _uniform_p(src[1::2][:, ok].ravel(), 0, 480) > P_MIN
+    x, y = src[0::2].astype(np.float64), src[1::2].astype(np.float64)
+    w = H[:, 2, 0, None] * x.T + H[:, 2, 1, None] * y.T + 1.0
+    assert w.min() >= 0.1
+    # the redraw only trims the corner of the perspective square that folds the frame
+    assert abs(np.mean(p < 0) - 0.5) < 0.02 and np.abs(p).max() <= 1e-3
+    u = H[:, 0, 0, None] * x.T + H[:, 0, 1, None] * y.T + H[:, 0, 2, None]
+    v = H[:, 1, 0, None] * x.T + H[:, 1, 1, None] * y.T + H[:, 1, 2, None]
+    nx = dst[0::2].T[ok] - (u / w)[ok]
+    ny = dst[1::2].T[ok] - (v / w)[ok]
+    for r in (nx.ravel(), ny.ravel()):
+        assert stats.kstest(r[:40000], "norm", args=(0.0, 0.5)).pvalue > P_MIN
+    # planted sets: some triangle of the source side is within 1e-3 px of a line
+    assert np.array_equal(np.nonzero(lab)[0], np.arange(0, 50000, 100))
+    pts = np.stack([x, y], axis=-1)[:, lab == 1]          # (4, k, 2)
+    hmin = np.full(pts.shape[1], np.inf)
+    for a, b, c in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+        for i, j, k in ((a, b, c), (b, c, a), (c, a, b)):
+            e = pts[j] - pts[i]
+            f = pts[k] - pts[i]
+            area = np.abs(e[:, 0] * f[:, 1] - e[:, 1] * f[:, 0])
+            hmin = np.minimum(hmin, area / np.hypot(e[:, 0], e[:, 1]))
+    assert hmin.max() <= 1e-3 + 1e-3         # 1e-3 px planted, plus float32 rounding of the points
+
+
+def _centred(H):
+    T = np.array([[1.0, 0, 320], [0, 1, 240], [0, 0, 1]])
+    Ti = np.array([[1.0, 0, -320], [0, 1, -240], [0, 0, 1]])
+    return Ti @ H @ T
+
+
+def test_correspondence_batch_distributions():
+    """Config-3 pairs: N_p ~ U{100..8000}, inlier ratio U[0.1, 0.9] with
+    round(ratio N) inliers; ground-truth H drawn as for the quadruples and
+    conjugated to act about the frame centre; inlier noise N(0, 1) px;
+    outliers uniform on both sides."""
+    b = synth.config3()
+    ns = np.diff(b.off)
+    assert ns.min() >= 100 and ns.max() <= 8000
+    # discrete uniform on {100..8000}: KS against the continuous law of N + U[0, 1)
+    jitter = np.random.default_rng(0).uniform(0, 1, ns.size)
+    assert _uniform_p(ns + jitter, 100, 8001) > P_MIN
+    assert _uniform_p(b.ratio, 0.1, 0.9) > P_MIN
+    n_in = np.add.reduceat(b.inlier.astype(np.int64), b.off[:-1])
+    assert np.array_equal(n_in, np.round(b.ratio * ns).astype(np.int64))
+    H = np.stack([_centred(h) for h in b.H_true])
+    s, th, tx, ty, p, q = _similarity_params(H)
+    for x, lo, hi in ((s, 0.5, 2.0), (th, -np.pi, np.pi), (tx, -100, 100), (p, -1e-3, 1e-3)):
+        assert _uniform_p(x, lo, hi) > P_MIN
+    # inlier residuals and outlier positions, over the first 64 pairs
+    res, outx = [], []
+    for k in range(64):
+        a, e = b.off[k], b.off[k + 1]
+        c = b.corr[:, a:e].astype(np.float64)
+        m = b.inlier[a:e]
+        Hk = b.H_true[k]
+        w = Hk[2, 0] * c[0] + Hk[2, 1] * c[1] + Hk[2, 2]
+        u = (Hk[0, 0] * c[0] + Hk[0, 1] * c[1] + Hk[0, 2]) / w
+        v = (Hk[1, 0] * c[0] + Hk[1, 1] * c[1] + Hk[1, 2]) / w
+        res += [(c[2] - u)[m], (c[3] - v)[m]]
+        outx.append(c[2][~m])
+    r = np.concatenate(res)
+    assert stats.kstest(r, "norm", args=(0.0, 1.0)).pvalue > P_MIN
+    assert _uniform_p(np.concatenate(outx), 0, 640) > P_MIN
+
+
+def test_patch_offsets_and_shifts():
+    pb = synth.patches(1024, 4, size=8)
+    assert _uniform_p(pb.offsets.ravel(), -32, 32) > P_MIN
+    counts = np.bincount((pb.shift + 16).ravel(), minlength=33)
+    assert counts.size == 33 and stats.chisquare(counts).pvalue > P_MIN

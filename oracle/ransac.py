@@ -196,15 +196,17 @@ def stopping_point(valid, counts, n, n_hyp_max, conf=0.99, round_size=64):
 
 
 def ransac_adaptive_ref(corr, n_hyp_max, tau, seed, pair=0, conf=0.99, round_size=64,
-                        band_px=1e-4):
+                        band_px=1e-4, full=None):
     """Adaptive single-pair reference. Hypotheses are evaluated in rounds of
     ``round_size`` (in index order); after each round the best so far gives
     eps = best_count / N, and the loop stops once the number evaluated m
     reaches min(required_iterations(eps), n_hyp_max). Returns the ransac_ref
     dict restricted to the evaluated prefix plus n_eval, and n_eval_min /
     n_eval_max: the stopping points when every exempt point is taken as an
-    inlier / an outlier."""
-    full = ransac_ref(corr, n_hyp_max, tau, seed, pair=pair, band_px=band_px)
+    inlier / an outlier. ``full``: the fixed-count reference of the same pair,
+    n_hyp_max, seed and band (ransac_ref), if already computed."""
+    if full is None:
+        full = ransac_ref(corr, n_hyp_max, tau, seed, pair=pair, band_px=band_px)
     n = np.asarray(corr).shape[1]
     valid, counts = full["valid"], full["counts"]
     m = stopping_point(valid, counts, n, n_hyp_max, conf, round_size)

@@ -113,10 +113,99 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// Maximum of a float over the 64 lanes of a wave (result in every lane).
+__device__ __forceinline__ float wave_max_f32(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Rows of points per group in the scoring loop: the unit whose float32
+// count is replaced by a float64 recount when a sign in it is not proven.
+constexpr int kGroup = 4;
+
+// Groups to recount, listed in LDS by the scoring loop (which leaves their
+// points out of its counts) and counted after it, when the loop's point
+// registers are free. Entry: the chunk's first point and (hypothesis |
+// group << 6 | wave << 9 | rows << 11). n counts every append; past kFixCap
+// the list has overflowed and every hypothesis is recounted in float64.
+constexpr uint32_t kFixCap = 512;
+struct FixList {
+  uint32_t n;
+  uint32_t e[kFixCap][2];
+};
+
+// Inliers of H (the float H, given as doubles) among `rows` (<= kGroup) rows
+// of 64 points, kWaves * 64 points apart from point ib of this lane (points
+// at or past n excluded), by the float64 test on the operands read from
+// memory (every row's loads issued before the first test; 32-bit byte
+// offsets from the plane bases, which the pair range keeps below 2^33).
+__device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *X1,
+                                              const float *Y1, const float *X2, const float *Y2,
+                                              uint32_t ib, uint32_t n, uint32_t rows,
+                                              const double *g) {
+  float x1[kGroup], y1[kGroup], x2[kGroup], y2[kGroup];
+#pragma unroll
+  for (int q = 0; q < kGroup; ++q) {
+    const uint32_t j = min(ib + q * kWaves * 64u, n - 1u);   // loads stay inside the pair
+    x1[q] = X1[j];
+    y1[q] = Y1[j];
+    x2[q] = X2[j];
+    y2[q] = Y2[j];
+  }
+  uint32_t c = 0u;
+#pragma unroll
+  for (int q = 0; q < kGroup; ++q) {
+    const uint32_t i = ib + q * kWaves * 64u;
+    const bool in = inlier_f64(g, x1[q], y1[q], x2[q], y2[q], a.tau);
+    c += __popcll(__ballot(in && i < n && static_cast<uint32_t>(q) < rows));
+  }
+  return c;
+}
+
+// After the scoring loop (and a workgroup barrier): apply the listed float64
+// recounts to cnt, or on overflow recount every valid hypothesis over all
+// points. Ends with a workgroup barrier.
+__device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const double (*H0s)[9],
+                           FixList *fx, uint64_t vmask, int nh, uint32_t *cnt) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
+  const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
+  const uint32_t ne = fx->n;
+  if (ne <= kFixCap) {
+    for (uint32_t k = wave; k < ne; k += kWaves) {
+      const uint32_t c0 = fx->e[k][0], w = fx->e[k][1];
+      const uint32_t h = w & 63u, g = (w >> 6) & 7u, wv = (w >> 9) & 3u, rows = (w >> 11) & 31u;
+      const uint32_t ib = c0 + (g * kGroup * kWaves + wv) * 64u + lane;
+      const uint32_t c64 = count_f64(a, X1, Y1, X2, Y2, ib, n, rows, H0s[h]);
+      if (lane == 0 && c64) atomicAdd(&cnt[h], c64);
+    }
+  } else {
+    for (int h = wave; h < nh; h += kWaves) {
+      if (!((vmask >> h) & 1ull)) continue;
+      uint32_t c = 0u;
+      for (uint32_t c0 = 0; c0 < n; c0 += kWaves * 64u * kGroup)
+        for (int wv = 0; wv < kWaves; ++wv)
+          c += count_f64(a, X1, Y1, X2, Y2, c0 + wv * 64u + lane, n, kGroup, H0s[h]);
+      if (lane == 0) cnt[h] = c;
+    }
+  }
+  __syncthreads();
+}
+
 // Count, for each hypothesis h < nh whose bit is set in vmask, the inliers
 // among the points [base, base + n) held in registers (P per lane); each wave
-// adds its counts into cnt[h] (LDS atomics). TAIL: the chunk runs past n and
-// lanes beyond it are masked out of the ballots.
+// adds its counts into cnt[h] (LDS atomics). Hs holds the hypotheses' scoring
+// forms. TAIL: the chunk runs past n and lanes beyond it are masked out of the
+// ballots.
+// Each wave decides its P x 64 points in float32, in groups of kGroup rows,
+// and keeps per lane and group the minimum over its points of
+// |e32| - |w| k1; where that reaches k0 for some lane (a point whose float32
+// sign is not proven, see error_bound), the group is listed in fx for a
+// float64 recount after the loop (fix_counts). The error bound's magnitudes
+// are the wave's maxima over its points, and its coefficients are computed
+// once per chunk, lane h for hypothesis h.
 // Under adaptive termination `stop` points at the pair's stopping hint and
 // `hb` is this item's round: every 8 hypotheses the wave compares hb with the
 // value it loaded at the previous check (the load's latency overlaps the 8
@@ -126,13 +215,14 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 template <int P, bool TAIL>
 __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
                                             const float *X2, const float *Y2, uint32_t c0,
-                                            uint32_t n, const float (*Hs)[9], uint64_t vmask,
-                                            int nh, uint32_t *cnt, const uint32_t *stop,
-                                            uint32_t hb) {
+                                            uint32_t n, const float (*Hs)[9],
+                                            uint64_t vmask, int nh, uint32_t *cnt,
+                                            FixList *fx, const uint32_t *stop, uint32_t hb) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   float x1[P], y1[P], x2[P], y2[P];
   uint64_t live[TAIL ? P : 1];
+  float m1 = 0.0f, m2 = 0.0f, m3 = 0.0f, m4 = 0.0f;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const uint32_t i = c0 + (p * kWaves + wave) * 64 + lane;
@@ -142,7 +232,18 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
     x2[p] = X2[j] * a.inv_tau;
     y2[p] = Y2[j] * a.inv_tau;
     if (TAIL) live[p] = __ballot(i < n);
+    m1 = fmaxf(m1, fabsf(x1[p]));
+    m2 = fmaxf(m2, fabsf(y1[p]));
+    m3 = fmaxf(m3, fabsf(x2[p]));
+    m4 = fmaxf(m4, fabsf(y2[p]));
   }
+  m1 = wave_max_f32(m1);
+  m2 = wave_max_f32(m2);
+  m3 = wave_max_f32(m3);
+  m4 = wave_max_f32(m4);
+  // lane h: error-bound coefficients of hypothesis h over this wave's points
+  float k1v = 0.0f, k0v = 0.0f;
+  if (lane < nh) error_bound(Hs[lane], m1, m2, m3, m4, k1v, k0v);
   uint32_t stop_seen =
       stop ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   for (int h = 0; h < nh; ++h) {
@@ -157,12 +258,42 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
     float hh[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) hh[k] = Hs[h][k];
+    const float k1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k1v), h));
+    const float k0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k0v), h));
+    // rows in groups of kGroup: per group the float32 count and the minimum
+    // over its points of |e32| - |w| k1 (the margin by which the sign is
+    // proven); a group with a sign not proven is listed for a float64 recount
+    // (which then supplies its whole count) instead of counted here
     uint32_t c = 0;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      uint64_t m = __ballot(inlier(hh, x1[p], y1[p], x2[p], y2[p]));
-      if (TAIL) m &= live[p];
-      c += __popcll(m);
+    for (int g = 0; g < (P + kGroup - 1) / kGroup; ++g) {
+      uint32_t cg = 0u;
+      float slack = __builtin_inff();
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
+        const int p = g * kGroup + q;
+        if (p < P) {
+          float w;
+          const float e = test_f32(hh, x1[p], y1[p], x2[p], y2[p], w);
+          uint64_t m = __ballot(e <= 0.0f);
+          if (TAIL) m &= live[p];
+          cg += __popcll(m);
+          slack = fminf(slack, fmaf(-fabsf(w), k1, fabsf(e)));
+        }
+      }
+      if (__builtin_expect(__ballot(slack <= k0) != 0ull, 0)) {
+        if (lane == 0) {
+          const uint32_t k = atomicAdd(&fx->n, 1u);
+          if (k < kFixCap) {
+            const uint32_t rows = min(kGroup, P - g * kGroup);
+            fx->e[k][0] = c0;
+            fx->e[k][1] = static_cast<uint32_t>(h) | (static_cast<uint32_t>(g) << 6) |
+                          (static_cast<uint32_t>(wave) << 9) | (rows << 11);
+          }
+        }
+      } else {
+        c += cg;
+      }
     }
     if (lane == 0 && c) atomicAdd(&cnt[h], c);
   }
@@ -176,7 +307,8 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
 template <int P>
 __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
                                            const float (*Hs)[9], uint64_t vmask, int nh,
-                                           uint32_t *cnt, const uint32_t *stop = nullptr,
+                                           uint32_t *cnt, FixList *fx,
+                                           const uint32_t *stop = nullptr,
                                            uint32_t hb = 0u) {
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
@@ -184,10 +316,10 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
   constexpr uint32_t kChunk8 = kWaves * 64 * 8;
   uint32_t c0 = 0;
   for (; c0 + kChunk <= n; c0 += kChunk)
-    if (!score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
+    if (!score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb)) return;
   if (P > 8) {
     for (; c0 + kChunk8 <= n; c0 += kChunk8)
-      if (!score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb)) return;
+      if (!score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb)) return;
   }
   if (c0 < n) {
     // fewer than kChunk8 points remain: 1 .. 8 rows of 64 points per wave
@@ -195,7 +327,7 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
     switch ((rows + kWaves - 1) / kWaves) {
 #define HG_TAIL(R) \
   case R:          \
-    score_chunk<R, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb); \
+    score_chunk<R, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb); \
     break;
       HG_TAIL(1)
       HG_TAIL(2)
@@ -205,7 +337,7 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
       HG_TAIL(6)
       HG_TAIL(7)
       default:
-        score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, stop, hb);
+        score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb);
 #undef HG_TAIL
     }
   }
@@ -279,8 +411,10 @@ __device__ void adaptive_hint(const RansacArgs &a, int p, uint32_t n_pts, int HB
 template <int HB>
 struct Smem {
   float H[HB][9];          // scoring form (rows 1-2 scaled by 1/tau)
+  double H0[HB][9];        // the float H, as doubles (for the float64 test)
   uint32_t valid[HB];
   uint32_t cnt[HB];
+  FixList fix;             // groups to recount in float64
   int64_t item;
   uint32_t skip;
 };
@@ -326,6 +460,8 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
       f = make_hypothesis(a.corr, a.ld, base, n, a.k0, a.k1, static_cast<uint32_t>(h0 + t),
                           static_cast<uint32_t>(p), h);
       score_form(h, a.inv_tau, sm.H[t]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sm.H0[t][k] = h[k];
       if (a.hbuf)
 #pragma unroll
         for (int k = 0; k < 9; ++k) a.hbuf[9ll * (h0 + t) + k] = h[k];
@@ -333,13 +469,15 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
     sm.valid[t] = (t < nh && f == 0u) ? 1u : 0u;
     sm.cnt[t] = 0u;
   }
+  if (threadIdx.x == 0) sm.fix.n = 0u;
   __syncthreads();
   // 2. score (validity as a wave-uniform bit mask)
   const int lane = threadIdx.x & 63;
   const uint64_t vmask = __ballot(lane < nh && sm.valid[lane] != 0u);
-  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt, adaptive ? &a.pst[p].stop : nullptr,
-                static_cast<uint32_t>(hb));
+  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt, &sm.fix,
+                adaptive ? &a.pst[p].stop : nullptr, static_cast<uint32_t>(hb));
   __syncthreads();
+  fix_counts(a, base, n, sm.H0, &sm.fix, vmask, nh, sm.cnt);
   if (adaptive) {
     // a wave may have given the round up: then it is at or past the stopping
     // round (which only decreases), and nothing of it is published
@@ -383,7 +521,7 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
 }
 
 template <int P, int HB, bool PERSISTENT>
-__global__ __launch_bounds__(kThreads) void ransac_kernel(RansacArgs a) {
+__global__ __launch_bounds__(kThreads, 5) void ransac_kernel(RansacArgs a) {
   __shared__ Smem<HB> sm;
   if (!PERSISTENT) {
     run_item<P, HB>(a, blockIdx.x, sm);
@@ -489,8 +627,9 @@ __global__ __launch_bounds__(kFinishThreads) void ransac_finish_kernel(RansacArg
   __syncthreads();
   if (threadIdx.x < 9) a.best_H[9 * p + threadIdx.x] = bestH[threadIdx.x];
   const bool any = skey != 0ull;
-  float hh[9];
-  score_form(bestH, a.inv_tau, hh);
+  double hh[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) hh[k] = bestH[k];
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   // 4 points per thread in flight (indices clamped into the pair for the loads)
@@ -508,8 +647,7 @@ __global__ __launch_bounds__(kFinishThreads) void ransac_finish_kernel(RansacArg
     for (int u = 0; u < 4; ++u) {
       const uint32_t i = i0 + static_cast<uint32_t>(u) * kFinishThreads;
       if (i < n)
-        a.mask[base + i] =
-            (any && inlier(hh, x1[u], y1[u], x2[u] * a.inv_tau, y2[u] * a.inv_tau)) ? 1 : 0;
+        a.mask[base + i] = (any && inlier_f64(hh, x1[u], y1[u], x2[u], y2[u], a.tau)) ? 1 : 0;
     }
   }
 }
@@ -537,12 +675,13 @@ __global__ __launch_bounds__(kThreads) void ransac_mask_kernel(RansacArgs a) {
     a.best_count[0] = any ? static_cast<int32_t>((key >> 32) - 1ull) : 0;
     a.best_hyp[0] = any ? static_cast<int32_t>(hyp) : -1;
   }
-  float hh[9];
-  score_form(bh, a.inv_tau, hh);
+  double hh[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) hh[k] = bh[k];
   const int n = a.n_single;
   const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
+    a.mask[i] = (any && inlier_f64(hh, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
 }
 
 // Resets keys, the queue and the adaptive state, and ranks pairs by size (largest
@@ -672,23 +811,28 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
                                                                const uint32_t *valid,
                                                                int32_t *counts) {
   __shared__ float Hs[HB][9];
+  __shared__ double H0s[HB][9];
   __shared__ uint32_t vs[HB];
   __shared__ uint32_t cnt[HB];
+  __shared__ FixList fix;
   const int h0 = blockIdx.x * HB;
   const int nh = min(HB, a.n_hyp - h0);
   for (int i = threadIdx.x; i < HB * 9; i += kThreads) {
     const float v = (i / 9 < nh) ? Hbuf[9 * h0 + i] : 0.0f;
     Hs[i / 9][i % 9] = (i % 9 < 6) ? v * a.inv_tau : v;   // scoring form
+    H0s[i / 9][i % 9] = v;
   }
   for (int i = threadIdx.x; i < HB; i += kThreads) {
     vs[i] = (i < nh) ? valid[h0 + i] : 0u;
     cnt[i] = 0u;
   }
+  if (threadIdx.x == 0) fix.n = 0u;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint64_t vmask = __ballot(lane < nh && vs[lane] != 0u);
-  score_hyps<P>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vmask, nh, cnt);
+  score_hyps<P>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vmask, nh, cnt, &fix);
   __syncthreads();
+  fix_counts(a, 0, static_cast<uint32_t>(a.n_single), H0s, &fix, vmask, nh, cnt);
   if (threadIdx.x < nh)
     counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(cnt[threadIdx.x]) : -1;
 }
@@ -721,10 +865,13 @@ __global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, cons
   const unsigned long long k = *key;
   const bool any = k != 0ull;
   const uint32_t hyp = any ? 0xFFFFFFFFu - static_cast<uint32_t>(k & 0xFFFFFFFFull) : 0u;
-  float bh[9], hh[9];
+  float bh[9];
+  double bd[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) bh[i] = any ? Hbuf[9 * hyp + i] : 0.0f;
-  score_form(bh, a.inv_tau, hh);
+  for (int i = 0; i < 9; ++i) {
+    bh[i] = any ? Hbuf[9 * hyp + i] : 0.0f;
+    bd[i] = bh[i];
+  }
   if (blockIdx.x == 0 && threadIdx.x < 9) a.best_H[threadIdx.x] = bh[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.best_count[0] = any ? static_cast<int32_t>((k >> 32) - 1ull) : 0;
@@ -733,7 +880,7 @@ __global__ __launch_bounds__(kThreads) void plain_mask_kernel(RansacArgs a, cons
   const int n = a.n_single;
   const float *X1 = a.corr, *Y1 = a.corr + a.ld, *X2 = a.corr + 2 * a.ld, *Y2 = a.corr + 3 * a.ld;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-    a.mask[i] = (any && inlier(hh, X1[i], Y1[i], X2[i] * a.inv_tau, Y2[i] * a.inv_tau)) ? 1 : 0;
+    a.mask[i] = (any && inlier_f64(bd, X1[i], Y1[i], X2[i], Y2[i], a.tau)) ? 1 : 0;
 }
 
 // ---- tuning --------------------------------------------------------------

@@ -124,6 +124,72 @@ def test_decision_band_covers_float32_evaluation(fused, case):
     assert n_band < 100
 
 
+def _fp32_certified(H, corr, tau, chunk=1024):
+    """Emulation (test only) of the scoring kernels' float32 test with its
+    error bound: e32 = ru'^2 + rv'^2 - w^2 with fused multiply-adds, and
+    k1, k0 from the magnitudes of each chunk of points. Returns (e32 <= 0,
+    certified), certified meaning |e32| > |w| k1 + k0."""
+    f32 = np.float32
+    u = 2.0 ** -24
+    c = f32(1.0) / f32(tau)
+    Hs = H.astype(f32).copy()
+    Hs[:, :2, :] = Hs[:, :2, :] * c
+    x1, y1 = (cc.astype(f32)[None] for cc in corr[:2])
+    x2, y2 = (cc.astype(f32)[None] * c for cc in corr[2:])
+
+    def fma(a, b, cc):   # product exact in float64, sum rounded there, then to float32
+        return (a.astype(np.float64) * b + cc).astype(f32)
+
+    def row(i):
+        return fma(Hs[:, i, 0, None], x1, fma(Hs[:, i, 1, None], y1, Hs[:, i, 2, None]))
+
+    uu, vv, w = row(0), row(1), row(2)
+    ru = fma(-x2, w, uu)
+    rv = fma(-y2, w, vv)
+    e = fma(-w, w, fma(rv, rv, ru * ru))
+    n = x1.shape[1]
+    cert = np.empty(e.shape, bool)
+    A = np.abs(Hs.astype(np.float64))
+    for a in range(0, n, chunk):
+        s = slice(a, min(n, a + chunk))
+        m1, m2, m3, m4 = (np.abs(v[0, s]).max() for v in (x1, y1, x2, y2))
+        su = A[:, 0, 0] * m1 + A[:, 0, 1] * m2 + A[:, 0, 2]
+        sv = A[:, 1, 0] * m1 + A[:, 1, 1] * m2 + A[:, 1, 2]
+        sw = A[:, 2, 0] * m1 + A[:, 2, 1] * m2 + A[:, 2, 2]
+        S = 4.1 * u * (su + sv + (m3 + m4) * sw)
+        k1 = 23 * u * sw + 5.5 * S
+        k0 = 14 * S * S + 11 * (u * sw) ** 2
+        cert[:, s] = np.abs(e[:, s]) > np.abs(w[:, s]) * k1[:, None] + k0[:, None]
+    return e <= 0, cert
+
+
+@pytest.mark.parametrize("case", ["config2", "horizon", "config3"])
+def test_float32_certificate_is_sound(case):
+    """Wherever the kernels' error bound certifies a float32 decision, it is
+    the float64 transfer-error decision (points within 1e-9 px of tau aside);
+    and the bound certifies all but a small fraction of the points."""
+    if case == "config2":
+        sets = [(synth.config2().corr, 4096, 2, 0)]
+    elif case == "horizon":
+        sets = [(synth.correspondences(1500, 0.5, 2500).corr, 4097, 77, 0)]
+    else:
+        b = synth.config3(64)
+        sets = [(b.corr[:, b.off[p]:b.off[p + 1]], 1024, 3, p) for p in range(0, 64, 4)]
+    tau = 3.0
+    n_cert = n_all = 0
+    for corr, nh, seed, pair in sets:
+        idx, H32, flags, valid = ransac.hypotheses(corr, nh, seed=seed, pair=pair)
+        for a in range(0, nh, 512):
+            H = H32[a:a + 512][valid[a:a + 512]]
+            d = ransac.transfer_error(H, corr)
+            got, cert = _fp32_certified(H, corr, tau)
+            care = cert & (np.abs(d - tau) > 1e-9)
+            assert np.array_equal(got[care], (d <= tau)[care])
+            n_cert += cert.sum()
+            n_all += cert.size
+    assert n_cert >= 0.999 * n_all
+
+
 def test_config2_planted_model_found():
     cs = synth.config2()
     ref = ransac.ransac_ref(cs.corr, 4096, 3.0, seed=2)

@@ -165,18 +165,43 @@ __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *
 
 // After the scoring loop (and a workgroup barrier): apply the listed float64
 // recounts to cnt, or on overflow recount every valid hypothesis over all
-// points. Ends with a workgroup barrier.
+// points. With `all` false (per-hypothesis counts are not an output), a
+// hypothesis is recounted only if it could still reach the best count among
+// the hypotheses counted exactly here: its listed points added to its count
+// reach that best (ties included). The others keep a count below their true
+// one, which stays below the best, so the maximum, its lowest index and the
+// mask do not change. ub: LDS scratch of HB words. Ends with a workgroup
+// barrier.
 __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const double (*H0s)[9],
-                           FixList *fx, uint64_t vmask, int nh, uint32_t *cnt) {
+                           FixList *fx, uint64_t vmask, int nh, uint32_t *cnt, bool all,
+                           uint32_t *ub) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
   const uint32_t ne = fx->n;
   if (ne <= kFixCap) {
+    uint32_t best = 0u;
+    if (!all && ne > 0u) {
+      // ub[h]: the count so far plus the listed points of h
+      for (int h = threadIdx.x; h < nh; h += kThreads) ub[h] = cnt[h];
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < ne; k += kThreads) {
+        const uint32_t w = fx->e[k][1];
+        atomicAdd(&ub[w & 63u], ((w >> 11) & 31u) * 64u);
+      }
+      __syncthreads();
+      // the best exact count: valid hypotheses with nothing listed
+      const bool exact = lane < nh && ((vmask >> lane) & 1ull) && ub[lane] == cnt[lane];
+      uint32_t v = exact ? cnt[lane] : 0u;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, o)));
+      best = v;
+    }
     for (uint32_t k = wave; k < ne; k += kWaves) {
       const uint32_t c0 = fx->e[k][0], w = fx->e[k][1];
       const uint32_t h = w & 63u, g = (w >> 6) & 7u, wv = (w >> 9) & 3u, rows = (w >> 11) & 31u;
+      if (!all && ub[h] < best) continue;   // cannot reach the best
       const uint32_t ib = c0 + (g * kGroup * kWaves + wv) * 64u + lane;
       const uint32_t c64 = count_f64(a, X1, Y1, X2, Y2, ib, n, rows, H0s[h]);
       if (lane == 0 && c64) atomicAdd(&cnt[h], c64);
@@ -414,6 +439,7 @@ struct Smem {
   double H0[HB][9];        // the float H, as doubles (for the float64 test)
   uint32_t valid[HB];
   uint32_t cnt[HB];
+  uint32_t ub[HB];         // scratch of fix_counts
   FixList fix;             // groups to recount in float64
   int64_t item;
   uint32_t skip;
@@ -477,7 +503,7 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt, &sm.fix,
                 adaptive ? &a.pst[p].stop : nullptr, static_cast<uint32_t>(hb));
   __syncthreads();
-  fix_counts(a, base, n, sm.H0, &sm.fix, vmask, nh, sm.cnt);
+  fix_counts(a, base, n, sm.H0, &sm.fix, vmask, nh, sm.cnt, a.hyp_counts != nullptr, sm.ub);
   if (adaptive) {
     // a wave may have given the round up: then it is at or past the stopping
     // round (which only decreases), and nothing of it is published
@@ -815,6 +841,7 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
   __shared__ uint32_t vs[HB];
   __shared__ uint32_t cnt[HB];
   __shared__ FixList fix;
+  __shared__ uint32_t ub[HB];
   const int h0 = blockIdx.x * HB;
   const int nh = min(HB, a.n_hyp - h0);
   for (int i = threadIdx.x; i < HB * 9; i += kThreads) {
@@ -832,7 +859,8 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
   const uint64_t vmask = __ballot(lane < nh && vs[lane] != 0u);
   score_hyps<P>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vmask, nh, cnt, &fix);
   __syncthreads();
-  fix_counts(a, 0, static_cast<uint32_t>(a.n_single), H0s, &fix, vmask, nh, cnt);
+  fix_counts(a, 0, static_cast<uint32_t>(a.n_single), H0s, &fix, vmask, nh, cnt,
+             a.hyp_counts != nullptr, ub);
   if (threadIdx.x < nh)
     counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(cnt[threadIdx.x]) : -1;
 }

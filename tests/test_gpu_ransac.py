@@ -253,6 +253,45 @@ def test_config3_persistent_graph_and_autotune():
     g.close()
 
 
+def test_outputs_without_hypothesis_counts():
+    """Without the per-hypothesis count output the kernels recount in float64
+    only the hypotheses that can still reach the best: best H, count, index
+    and mask are those of the run with every count exact (single pair, plain
+    and fused; the 512-pair batch)."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    from paper_2402_18008_amd import _abi
+    cs = synth.config2()
+    corr = torch.from_numpy(cs.corr).cuda()
+    n, nh = corr.shape[1], 4096
+    for name in ("hg_ransac", "hg_ransac_plain"):
+        announce(f"{name} config2 with and without hyp_counts")
+        outs = []
+        for with_counts in (True, False):
+            ws = torch.empty(hgpu.hg_ransac_ws_bytes(n, nh), dtype=torch.uint8, device="cuda")
+            bh = torch.empty(9, device="cuda")
+            bc = torch.empty(1, dtype=torch.int32, device="cuda")
+            bi = torch.empty(1, dtype=torch.int32, device="cuda")
+            mk = torch.empty(n, dtype=torch.uint8, device="cuda")
+            hc = torch.empty(nh, dtype=torch.int32, device="cuda") if with_counts else None
+            _abi.call(name, corr.data_ptr(), n, n, nh, TAU, 2, bh.data_ptr(), bc.data_ptr(),
+                      bi.data_ptr(), mk.data_ptr(), hc.data_ptr() if with_counts else None,
+                      ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            outs.append([t.cpu().numpy() for t in (bh, bc, bi, mk)])
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), name
+    cb = synth.config3()
+    announce("batched config3 with and without hyp_counts")
+    full = batched(cb, hyp_counts=True)
+    full.run()
+    fast = batched(cb, hyp_counts=False)
+    fast.run()
+    torch.cuda.synchronize()
+    for k in ("best_H", "best_count", "best_hyp", "mask"):
+        assert torch.equal(getattr(full, k), getattr(fast, k)), k
+
+
 # ---- adaptive termination ------------------------------------------------------
 
 def check_adaptive_pair(corr, n_hyp_max, seed, pair, got, label, full=None):

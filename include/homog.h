@@ -163,6 +163,19 @@ int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
                     uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* hg_ransac without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Arguments and results are those of hg_ransac; the
+ * workspace is the library's own static device array of 622592 bytes, one per
+ * GPU, held until the process ends (its address is looked up on the first
+ * call on each device). n_hyp <= 16384 (HG_EINVAL beyond). No allocation of
+ * any kind happens in the call. Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (concurrent streams or threads) race
+ * and must be serialised by the caller.                                       */
+int hg_ransac_noalloc(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,
+                      uint64_t seed, float *best_H, int32_t *best_count, int32_t *best_hyp,
+                      uint8_t *inlier_mask, int32_t *hyp_counts, void *stream);
+
 /* ---- batched RANSAC over many uneven pairs --------------------------------
  * Pair p owns points [off[p], off[p+1]) of the concatenated planes (corr at
  * stride ld >= off[n_pairs]); every pair runs n_hyp hypotheses with Philox

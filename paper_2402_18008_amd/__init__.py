@@ -194,6 +194,28 @@ def hg_ransac_plain(corr, n_hyp, thresh, seed, hyp_counts=True, ws=None, stream=
     return _ransac("hg_ransac_plain", corr, n_hyp, thresh, seed, hyp_counts, ws, stream)
 
 
+def hg_ransac_noalloc(corr, n_hyp, thresh, seed, hyp_counts=True, out=None, stream=None):
+    """``hg_ransac`` on the library's own static workspace (no allocation in
+    the call; n_hyp <= 16384). ``out``: the result dict of a previous call to
+    reuse (its tensors are overwritten), else new output tensors are made
+    here. Calls that overlap on one GPU race (one workspace per GPU)."""
+    ld, n = _corr_planes(corr)
+    dev = corr.device
+    if out is None:
+        out = dict(best_H=torch.empty(9, dtype=torch.float32, device=dev),
+                   best_count=torch.empty(1, dtype=torch.int32, device=dev),
+                   best_hyp=torch.empty(1, dtype=torch.int32, device=dev),
+                   mask=torch.empty(n, dtype=torch.uint8, device=dev),
+                   hyp_counts=(torch.empty(n_hyp, dtype=torch.int32, device=dev)
+                               if hyp_counts else None))
+    hc = out["hyp_counts"]
+    _abi.call("hg_ransac_noalloc", corr.data_ptr(), n, ld, int(n_hyp), float(thresh),
+              int(seed) & (2**64 - 1), out["best_H"].data_ptr(), out["best_count"].data_ptr(),
+              out["best_hyp"].data_ptr(), out["mask"].data_ptr(),
+              hc.data_ptr() if hc is not None else None, _stream(stream))
+    return out
+
+
 def hg_ransac_batched_ws_bytes(n_pairs, n_hyp):
     return int(_abi.lib().hg_ransac_batched_ws_bytes(int(n_pairs), int(n_hyp)))
 

@@ -42,6 +42,7 @@ SIGNATURES = {
     "hg_ransac_ws_bytes": (sz, [i32, i32]),
     "hg_ransac": (C.c_int, [vp, i32, i64, i32, f32, u64, vp, vp, vp, vp, vp, vp, sz, vp]),
     "hg_ransac_plain": (C.c_int, [vp, i32, i64, i32, f32, u64, vp, vp, vp, vp, vp, vp, sz, vp]),
+    "hg_ransac_noalloc": (C.c_int, [vp, i32, i64, i32, f32, u64, vp, vp, vp, vp, vp, vp]),
     "hg_ransac_batched_ws_bytes": (sz, [i32, i32]),
     "hg_ransac_batched": (C.c_int, [vp, i64, vp, i32, i32, f32, u64, C.POINTER(Tuning),
                                     vp, vp, vp, vp, vp, vp, sz, vp]),

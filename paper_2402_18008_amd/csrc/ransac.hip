@@ -1139,24 +1139,19 @@ static int check_batched(const float *corr, int64_t ld, const int64_t *off, int3
 
 using namespace hg;
 
-extern "C" size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp) {
-  (void)n_pts;
-  if (n_hyp < 1) n_hyp = 1;
-  // fused: every hypothesis's H and each work item's best key (at least 4
-  // hypotheses per item); plain: H buffer, validity, counts and the argmax key
-  return std::max(align256(36ull * n_hyp) + align256(8ull * ((n_hyp + 3) / 4)),
-                  plain_ws_bytes(n_hyp));
+namespace hg {
+
+// Workspace of the fused single-pair form: every hypothesis's H and each work
+// item's best key (at least 4 hypotheses per item).
+static size_t fused_ws_bytes(int32_t n_hyp) {
+  return align256(36ull * n_hyp) + align256(8ull * ((n_hyp + 3) / 4));
 }
 
-extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
-                         float thresh, uint64_t seed, float *best_H, int32_t *best_count,
-                         int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts, void *ws,
-                         size_t ws_bytes, void *stream) {
-  clear_error();
-  if (int st = check_single(corr, n_pts, ld, n_hyp, thresh, best_H, best_count, best_hyp,
-                            inlier_mask, ws, ws_bytes, hg_ransac_ws_bytes(n_pts, n_hyp)))
-    return st;
-  const hipStream_t s = as_stream(stream);
+// Enqueue the fused single-pair form (scoring kernel + mask kernel) with
+// workspace ws (validated by the caller).
+static int launch_fused(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp, float thresh,
+                        uint64_t seed, float *best_H, int32_t *best_count, int32_t *best_hyp,
+                        uint8_t *inlier_mask, int32_t *hyp_counts, void *ws, hipStream_t s) {
   // about two workgroups per compute unit when the hypothesis count allows it
   int HB = 4;
   while (HB < 64 && static_cast<int64_t>(HB) * 2 * device_cus() < n_hyp) HB *= 2;
@@ -1172,6 +1167,77 @@ extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n
   const int mb = std::max(1, std::min(1024, (n_pts + kThreads - 1) / kThreads));
   hipLaunchKernelGGL(ransac_mask_kernel, dim3(mb), dim3(kThreads), 0, s, a);
   return launched("ransac_mask_kernel");
+}
+
+// The library's own workspace for hg_ransac_noalloc: a static device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code never uses this name as an address: the device address is looked
+// up once per device (hipGetSymbolAddress) and kept in g_noalloc_ws.
+constexpr int32_t kNoAllocMaxHyp = 16384;
+constexpr size_t kNoAllocBytes = 36ull * kNoAllocMaxHyp + 8ull * (kNoAllocMaxHyp / 4);
+static_assert(kNoAllocBytes % 256 == 0, "whole 256-byte blocks");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ws[64] = {nullptr};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+static int noalloc_ws(void **out) {
+  int dev = 0;
+  HG_HIP(hipGetDevice(&dev));
+  HG_REQUIRE(dev >= 0 && dev < 64, "hg_ransac_noalloc: device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ws[dev]) {
+    void *ptr = nullptr;
+    HG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    HG_REQUIRE(ptr != nullptr && aligned(ptr, 256), "hg_ransac_noalloc: bad workspace address");
+    g_noalloc_ws[dev] = ptr;
+  }
+  *out = g_noalloc_ws[dev];
+  return HG_OK;
+}
+
+}  // namespace hg
+
+extern "C" size_t hg_ransac_ws_bytes(int32_t n_pts, int32_t n_hyp) {
+  (void)n_pts;
+  if (n_hyp < 1) n_hyp = 1;
+  // fused: H of every hypothesis and per-item best keys; plain: H buffer,
+  // validity, counts and the argmax key
+  return std::max(fused_ws_bytes(n_hyp), plain_ws_bytes(n_hyp));
+}
+
+extern "C" int hg_ransac(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
+                         float thresh, uint64_t seed, float *best_H, int32_t *best_count,
+                         int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts, void *ws,
+                         size_t ws_bytes, void *stream) {
+  clear_error();
+  if (int st = check_single(corr, n_pts, ld, n_hyp, thresh, best_H, best_count, best_hyp,
+                            inlier_mask, ws, ws_bytes, hg_ransac_ws_bytes(n_pts, n_hyp)))
+    return st;
+  return launch_fused(corr, n_pts, ld, n_hyp, thresh, seed, best_H, best_count, best_hyp,
+                      inlier_mask, hyp_counts, ws, as_stream(stream));
+}
+
+extern "C" int hg_ransac_noalloc(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,
+                                 float thresh, uint64_t seed, float *best_H, int32_t *best_count,
+                                 int32_t *best_hyp, uint8_t *inlier_mask, int32_t *hyp_counts,
+                                 void *stream) {
+  clear_error();
+  HG_REQUIRE(n_hyp <= kNoAllocMaxHyp,
+             "hg_ransac_noalloc: n_hyp = %d exceeds the maximum of %d (use hg_ransac with a "
+             "caller workspace)", n_hyp, kNoAllocMaxHyp);
+  // arguments first (host only; any aligned non-null address stands for the
+  // workspace here), then the workspace's device address
+  if (int st = check_single(corr, n_pts, ld, n_hyp, thresh, best_H, best_count, best_hyp,
+                            inlier_mask, reinterpret_cast<void *>(256), kNoAllocBytes,
+                            fused_ws_bytes(n_hyp)))
+    return st;
+  void *ws = nullptr;
+  if (int st = noalloc_ws(&ws)) return st;
+  return launch_fused(corr, n_pts, ld, n_hyp, thresh, seed, best_H, best_count, best_hyp,
+                      inlier_mask, hyp_counts, ws, as_stream(stream));
 }
 
 extern "C" int hg_ransac_plain(const float *corr, int32_t n_pts, int64_t ld, int32_t n_hyp,

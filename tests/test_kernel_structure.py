@@ -33,7 +33,10 @@ def compile_asm(tmp_path):
 
 
 def functions(asm):
+    names = set(re.findall(r"^\s*\.type\s+(_ZN2hg\S+),@function", asm, re.M))
     for m in re.finditer(r"^(_ZN2hg\S+):", asm, re.M):
+        if m.group(1) not in names:        # a device variable, not a function
+            continue
         body = asm[m.end():]
         body = body[:body.index(".Lfunc_end")]
         yield m.group(1), body

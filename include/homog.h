@@ -281,11 +281,13 @@ void hg_graph_destroy(hg_graph *g);
  * Source: the rectangle with upper-left vertex (x0, y0), width w and aspect
  * ratio r = width / height (Sec. 5.3). offsets: B x 4 x 2 floats, corner
  * order TL, TR, BR, BL; target corners = source corners + offsets.
- * hg_aca_rect_fwd: H (B x 9 doubles) by Algorithm 1 (tensorised ACA for a
- *   rectangle), double precision inside, not rescaled (each h_ij is the
- *   polynomial of the corners that the algorithm defines).
+ * hg_aca_rect_fwd: H (B x 9 doubles) mapping the rectangle to the target
+ *   quadrilateral (the rectangle case of ACA that Algorithm 1 tensorises,
+ *   Sec. 5.3): ACA (Sec. 4) with the source points M N P Q at the corners TL,
+ *   TR, BL, BR, at ACA's own scale (no rescaling, as hg_aca_fwd), double
+ *   precision inside.
  * hg_aca_rect_bwd: grad_offsets (B x 8 floats) = (dH/d offsets)^T grad_H,
- *   grad_H B x 9 doubles.
+ *   grad_H B x 9 doubles (ACA's reverse mode in the target points).
  * Errors: B < 0, w or r not finite and > 0, non-finite x0/y0, NULL pointer
  * with B > 0 -> HG_EINVAL; B == 0 is a no-op.                                */
 int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w, float r,
@@ -311,7 +313,9 @@ int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t
  * p = (x, y) of an h x w output (x = column), sample img at pi(adj(H) p)
  * (adj(H) ~ H^-1) bilinearly, x0 = floor(x), taps outside the image reading
  * 0; loss[b] = mean_p |I_w(p) - tgt(p)| (float). img, tgt: B x h x w floats.
- * Per-pixel arithmetic is double precision.
+ * The sample position and the floor are double precision (the reciprocal to
+ * ~2^-46 relative); bilinear weights, taps, residual and gradient terms are
+ * float, with per-patch sums accumulated in double.
  * hg_warp_l1_bwd recomputes everything from H (nothing per pixel is stored)
  * and writes grad_H (B x 9 doubles) = grad_loss[b] * dloss[b]/dH_b, with
  * d|r|/dr = sign(r) (0 at 0) and the floor treated as constant.
@@ -326,11 +330,16 @@ int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const fl
  * whose source rectangle has its corners at the pixel centres: the same
  * arithmetic as hg_aca_rect_fwd(offsets, 0, 0, w - 1, (w - 1) / (h - 1))
  * followed by hg_warp_l1_fwd, resp. hg_warp_l1_bwd and hg_aca_rect_bwd, in
- * one launch each (one workgroup per patch; Algorithm 1 and its reverse mode
- * run in the workgroup's first lane, H stays on chip).
+ * one launch each (one workgroup per patch; ACA and its reverse mode run in
+ * the workgroup's first lane, H stays on chip).
  *   hg_photometric_fwd: loss (B floats).
  *   hg_photometric_bwd: grad_offsets (B x 4 x 2 floats) = grad_loss[b] *
- *     dloss[b]/d offsets_b.
+ *     dloss[b]/d offsets_b (recomputes the forward quantities).
+ *   hg_photometric_fwd_grad: loss and grad_unit (B x 4 x 2 floats) =
+ *     dloss[b]/d offsets_b in one pass over img and tgt (the loss is linear
+ *     in grad_loss, so a later backward only scales grad_unit:
+ *     hg_scale_grad(grad_unit, grad_loss, B, grad_offsets) writes
+ *     grad_offsets[b] = grad_loss[b] * grad_unit[b], 8 floats per patch).
  * Errors: B < 0, h or w outside [2, 32768], h w > 2^29, NULL pointer with B > 0 ->
  * HG_EINVAL; B == 0 is a no-op.                                            */
 int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt, int32_t B,
@@ -338,6 +347,11 @@ int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt,
 int hg_photometric_bwd(const float *offsets, const float *img, const float *tgt,
                        const float *grad_loss, int32_t B, int32_t h, int32_t w,
                        float *grad_offsets, void *stream);
+int hg_photometric_fwd_grad(const float *offsets, const float *img, const float *tgt,
+                            int32_t B, int32_t h, int32_t w, float *loss, float *grad_unit,
+                            void *stream);
+int hg_scale_grad(const float *grad_unit, const float *grad_loss, int32_t B,
+                  float *grad_offsets, void *stream);
 
 /* Iterative refinement of 4-point offsets: the structure of iterative deep
  * homography networks (six solver calls per forward pass in the deep-pipeline

@@ -418,7 +418,7 @@ def _c(t, name, dtype=torch.float32):
 
 def hg_aca_rect_fwd(offsets, x0, y0, w, r, stream=None):
     """H (B, 9) float64 from offsets (B, 4, 2) float32 [TL, TR, BR, BL] by
-    Algorithm 1."""
+    ACA with the source corners at the rectangle's."""
     _c(offsets, "offsets")
     B = offsets.shape[0]
     H = torch.empty((B, 9), dtype=torch.float64, device=offsets.device)
@@ -548,8 +548,9 @@ def hg_warp_bwd_from_grad(H, img, grad_warped, stream=None):
 
 
 class ACARect(torch.autograd.Function):
-    """offsets (B, 4, 2) float32 -> H (B, 9) float64 by Algorithm 1; backward
-    by the hand-written reverse-mode kernel."""
+    """offsets (B, 4, 2) float32 -> H (B, 9) float64 by ACA with the source
+    corners at the rectangle's; backward by the hand-written reverse-mode
+    kernel."""
 
     @staticmethod
     def forward(ctx, offsets, x0, y0, w, r):
@@ -583,7 +584,7 @@ class WarpL1(torch.autograd.Function):
 
 
 def hg_photometric_fwd(offsets, img, tgt, stream=None):
-    """Fused offsets (B, 4, 2) -> per-patch loss (B,) (Algorithm 1 + warp + L1)."""
+    """Fused offsets (B, 4, 2) -> per-patch loss (B,) (ACA + warp + L1)."""
     _c(offsets, "offsets")
     B, h, w = _img3(img, "img")
     _img3(tgt, "tgt")
@@ -605,9 +606,58 @@ def hg_photometric_bwd(offsets, img, tgt, grad_loss, stream=None):
     return g
 
 
+def hg_photometric_fwd_grad(offsets, img, tgt, stream=None):
+    """Loss and its gradient in one pass: (loss (B,), grad_unit (B, 4, 2)) with
+    grad_unit[b] = dloss_b/d offsets_b."""
+    _c(offsets, "offsets")
+    B, h, w = _img3(img, "img")
+    _img3(tgt, "tgt")
+    loss = torch.empty(B, dtype=torch.float32, device=img.device)
+    g = torch.empty((B, 4, 2), dtype=torch.float32, device=img.device)
+    _abi.call("hg_photometric_fwd_grad", offsets.data_ptr(), img.data_ptr(), tgt.data_ptr(), B, h,
+              w, loss.data_ptr(), g.data_ptr(), _stream(stream))
+    return loss, g
+
+
+def hg_scale_grad(grad_unit, grad_loss, stream=None):
+    """grad_loss[b] * grad_unit[b] for (B, 4, 2) grad_unit, (B,) grad_loss."""
+    _c(grad_unit, "grad_unit")
+    _c(grad_loss, "grad_loss")
+    B = grad_unit.shape[0]
+    if tuple(grad_unit.shape) != (B, 4, 2) or grad_loss.numel() != B:
+        raise ValueError("grad_unit must be (B, 4, 2) and grad_loss (B,)")
+    out = torch.empty_like(grad_unit)
+    _abi.call("hg_scale_grad", grad_unit.data_ptr(), grad_loss.data_ptr(), B, out.data_ptr(),
+              _stream(stream))
+    return out
+
+
 class PhotometricL1(torch.autograd.Function):
+    """offsets -> per-patch loss. When the offsets need a gradient, one launch
+    computes the loss and its gradient together (img and tgt are read once;
+    8 floats per patch are kept) and the backward scales that gradient by
+    grad_loss; otherwise a loss-only launch."""
+
+    @staticmethod
+    def forward(ctx, offsets, img, tgt):
+        offsets, img, tgt = offsets.contiguous(), img.contiguous(), tgt.contiguous()
+        if ctx.needs_input_grad[0]:
+            loss, g = hg_photometric_fwd_grad(offsets, img, tgt)
+            ctx.save_for_backward(g)
+            return loss
+        return hg_photometric_fwd(offsets, img, tgt)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        (g,) = ctx.saved_tensors
+        gl = grad_loss.to(torch.float32).contiguous()
+        return hg_scale_grad(g, gl), None, None
+
+
+class PhotometricL1Recompute(torch.autograd.Function):
     """offsets -> per-patch loss in one fused launch; backward in one fused
-    launch that recomputes H, the warp and Algorithm 1's reverse mode."""
+    launch that recomputes H, the warp and ACA's reverse mode (nothing per
+    patch is kept but the inputs)."""
 
     @staticmethod
     def forward(ctx, offsets, img, tgt):
@@ -625,8 +675,11 @@ class PhotometricL1(torch.autograd.Function):
 def photometric_loss(offsets, img, tgt, fused=True):
     """Per-patch loss of the 4-point-offset pipeline for h x w patches with
     corners at the pixel centres (0, 0) .. (w-1, h-1); differentiable in
-    offsets. ``fused=False`` composes the separate ACARect and WarpL1 stages
-    (same arithmetic, four launches instead of two)."""
+    offsets. ``fused=True``: single-pass loss and gradient (PhotometricL1);
+    ``"recompute"``: fused forward and recomputing backward launches;
+    ``False``: the separate ACARect and WarpL1 stages (same arithmetic)."""
+    if fused == "recompute":
+        return PhotometricL1Recompute.apply(offsets, img, tgt)
     if fused:
         return PhotometricL1.apply(offsets, img, tgt)
     h, w = img.shape[-2:]
@@ -636,7 +689,7 @@ def photometric_loss(offsets, img, tgt, fused=True):
 
 class Refine:
     """Iterative refinement of 4-point offsets (hg_refine): ``iters`` rounds
-    of Algorithm 1 -> warp + L1 backward -> reverse mode -> offsets -= step *
+    of ACA -> warp + L1 backward -> reverse mode -> offsets -= step *
     grad on h x w patches (one fused launch per iteration); ``run()`` launches eagerly,
     ``graph()`` captures the same sequence for replay. ``offsets`` (B, 4, 2)
     float32 is updated in place; ``loss`` (B,) holds the final loss."""

@@ -63,6 +63,8 @@ SIGNATURES = {
     "hg_aca_bwd": (C.c_int, [vp, vp, vp, i32, vp, vp, vp]),
     "hg_photometric_fwd": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, vp]),
     "hg_photometric_bwd": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, vp, vp]),
+    "hg_photometric_fwd_grad": (C.c_int, [vp, vp, vp, i32, i32, i32, vp, vp, vp]),
+    "hg_scale_grad": (C.c_int, [vp, vp, i32, vp, vp]),
     "hg_refine": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp]),
     "hg_refine_graph_create": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, vp, vp, vp,
                                          C.POINTER(vp)]),

@@ -1,13 +1,17 @@
-// Differentiable 4-point-offset pipeline: offsets -> H (Algorithm 1, the
-// tensorised ACA for a rectangle) -> bilinear inverse warp -> L1 loss, with
-// hand-written backward kernels that recompute per-pixel state from H.
+// Differentiable 4-point-offset pipeline: offsets -> H (ACA with the source
+// corners fixed at a rectangle's) -> bilinear inverse warp -> L1 loss, with
+// hand-written backward kernels that recompute per-pixel state from H, and a
+// single-pass kernel that computes the loss and its gradient together.
 //
-// H is carried in double precision between the stages, and every per-pixel
-// step (sample position, bilinear weights, residual, gradient terms) runs in
-// double on the float images: a float sample position (error ~1e-5 px) would
-// move pixels across the kinks of the bilinear and L1 terms and change the
-// gradient by ~1e-3 relative. One 256-thread workgroup per patch; per-patch
-// sums are accumulated per thread and across the workgroup in double.
+// H and G = adj(H) are double precision, and so is each pixel's sample
+// position: q = G (x, y, 1) and the projective division, whose reciprocal is
+// a float estimate refined by one double Newton step (relative error ~2^-46,
+// ~1e-12 px at patch scale). The floor that picks the bilinear cell is taken
+// on that position, so cell choices (the kinks of the sampler) are those of
+// float64 arithmetic. Everything after the floor runs in float: the bilinear
+// weights (the cell fractions rounded to float), taps, residual, sign and the
+// gradient terms; per-thread float partial sums are folded into double every
+// 16 pixels, and per-patch sums across the workgroup are double.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -20,143 +24,78 @@ namespace hg {
 
 constexpr int kDiffThreads = 256;
 
-// Target corners from the offsets (TL, TR, BR, BL) of the rectangle with
-// upper-left (x0, y0), width w and aspect ratio r, as ACA points M N P Q.
-struct RectCorners {
-  double M2x, M2y, N2x, N2y, P2x, P2y, Q2x, Q2y;
+// A rectangle with upper-left (x0, y0), width w and aspect ratio r = width /
+// height, as ACA's source points M N P Q = TL, TR, BL, BR.
+struct RectArgs {
+  double x0, y0, w, r;
 };
 
-__device__ __forceinline__ RectCorners rect_targets(const float *o, double x0, double y0, double w,
-                                                    double r) {
-  const double hgt = w / r;
-  RectCorners c;
-  c.M2x = x0 + static_cast<double>(o[0]);
-  c.M2y = y0 + static_cast<double>(o[1]);
-  c.N2x = x0 + w + static_cast<double>(o[2]);
-  c.N2y = y0 + static_cast<double>(o[3]);
-  c.Q2x = x0 + w + static_cast<double>(o[4]);
-  c.Q2y = y0 + hgt + static_cast<double>(o[5]);
-  c.P2x = x0 + static_cast<double>(o[6]);
-  c.P2y = y0 + hgt + static_cast<double>(o[7]);
-  return c;
+__device__ __forceinline__ void rect_source(const RectArgs &ra, double s[8]) {
+  const double x1 = ra.x0 + ra.w, y1 = ra.y0 + ra.w / ra.r;
+  s[0] = ra.x0;
+  s[1] = ra.y0;
+  s[2] = x1;
+  s[3] = ra.y0;
+  s[4] = ra.x0;
+  s[5] = y1;
+  s[6] = x1;
+  s[7] = y1;
 }
 
-// Algorithm 1: H = [h1 h2 h3] (columns) from the target corners.
-__device__ __forceinline__ void rect_aca(const RectCorners &k, double x0, double y0, double w,
-                                         double r, double H[9]) {
-  const double d1[3] = {k.N2x - k.M2x, k.P2x - k.M2x, k.Q2x - k.M2x};
-  const double d2[3] = {k.N2y - k.M2y, k.P2y - k.M2y, k.Q2y - k.M2y};
-  const double c0 = d1[1] * d2[2] - d1[2] * d2[1];
-  const double c1 = d1[2] * d2[0] - d1[0] * d2[2];
-  const double c2 = d1[0] * d2[1] - d1[1] * d2[0];
-  const double S = c0 + c1 + c2;
-  const double b[3] = {S * k.M2x, S * k.M2y, S};
-  const double h1[3] = {c0 * k.N2x - b[0], c0 * k.N2y - b[1], c0 - b[2]};
-  const double h2[3] = {r * (c1 * k.P2x - b[0]), r * (c1 * k.P2y - b[1]), r * (c1 - b[2])};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    H[3 * i + 0] = h1[i];
-    H[3 * i + 1] = h2[i];
-    H[3 * i + 2] = w * b[i] - x0 * h1[i] - y0 * h2[i];
-  }
+// Target points M N P Q = source corners + offsets (offset order TL TR BR BL).
+__device__ __forceinline__ void rect_target(const float *o, const double s[8], double d[8]) {
+  d[0] = s[0] + static_cast<double>(o[0]);
+  d[1] = s[1] + static_cast<double>(o[1]);
+  d[2] = s[2] + static_cast<double>(o[2]);
+  d[3] = s[3] + static_cast<double>(o[3]);
+  d[6] = s[6] + static_cast<double>(o[4]);
+  d[7] = s[7] + static_cast<double>(o[5]);
+  d[4] = s[4] + static_cast<double>(o[6]);
+  d[5] = s[5] + static_cast<double>(o[7]);
 }
 
-__global__ void rect_fwd_kernel(const float *__restrict__ off, int B, double x0, double y0,
-                                double w, double r, double *__restrict__ H) {
+// H (row-major, ACA's own scale) of one patch from its offsets.
+__device__ __forceinline__ void rect_h(const float *o, const RectArgs &ra, double H[9]) {
+  double s[8], d[8];
+  rect_source(ra, s);
+  rect_target(o, s, d);
+  (void)aca_solve(s, d, H);
+}
+
+// dL/d offsets (order TL TR BR BL) from dL/dH, through ACA's reverse mode
+// with respect to the target points.
+__device__ __forceinline__ void rect_h_vjp(const float *o, const RectArgs &ra, const double gH[9],
+                                           double g[8]) {
+  double s[8], d[8], gs[8], gd[8];
+  rect_source(ra, s);
+  rect_target(o, s, d);
+  aca_vjp(s, d, gH, gs, gd);
+  g[0] = gd[0];
+  g[1] = gd[1];
+  g[2] = gd[2];
+  g[3] = gd[3];
+  g[4] = gd[6];
+  g[5] = gd[7];
+  g[6] = gd[4];
+  g[7] = gd[5];
+}
+
+__global__ void rect_fwd_kernel(const float *__restrict__ off, int B, RectArgs ra,
+                                double *__restrict__ H) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  const RectCorners k = rect_targets(off + 8 * b, x0, y0, w, r);
   double h[9];
-  rect_aca(k, x0, y0, w, r, h);
+  rect_h(off + 8 * b, ra, h);
 #pragma unroll
   for (int i = 0; i < 9; ++i) H[9 * b + i] = h[i];
 }
 
-// Reverse mode through Algorithm 1 (each step's adjoint in reverse order) for
-// one patch: offsets o (8), dL/dH gHb (9) -> dL/d offsets (8, order TL TR BR BL).
-__device__ __forceinline__ void rect_bwd_one(const float *o, const double *gHb, double x0,
-                                             double y0, double w, double r, double *gout) {
-  const RectCorners k = rect_targets(o, x0, y0, w, r);
-  const double d1[3] = {k.N2x - k.M2x, k.P2x - k.M2x, k.Q2x - k.M2x};
-  const double d2[3] = {k.N2y - k.M2y, k.P2y - k.M2y, k.Q2y - k.M2y};
-  const double c0 = d1[1] * d2[2] - d1[2] * d2[1];
-  const double c1 = d1[2] * d2[0] - d1[0] * d2[2];
-  const double c2 = d1[0] * d2[1] - d1[1] * d2[0];
-  const double S = c0 + c1 + c2;
-  double g1[3], g2[3], g3[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    g1[i] = gHb[3 * i + 0];
-    g2[i] = gHb[3 * i + 1];
-    g3[i] = gHb[3 * i + 2];
-  }
-  double gb[3], gM2x = 0, gM2y = 0, gN2x = 0, gN2y = 0, gP2x = 0, gP2y = 0, gQ2x = 0, gQ2y = 0;
-  // h3 = w b - x0 h1 - y0 h2
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    gb[i] = w * g3[i];
-    g1[i] -= x0 * g3[i];
-    g2[i] -= y0 * g3[i];
-  }
-  // h2 = r (c1 p2 - b), p2 = (P2x, P2y, 1)
-  double e[3] = {r * g2[0], r * g2[1], r * g2[2]};
-  double gc1 = e[0] * k.P2x + e[1] * k.P2y + e[2];
-  gP2x += e[0] * c1;
-  gP2y += e[1] * c1;
-  // h1 = c0 n2 - b, n2 = (N2x, N2y, 1)
-  double gc0 = g1[0] * k.N2x + g1[1] * k.N2y + g1[2];
-  gN2x += g1[0] * c0;
-  gN2y += g1[1] * c0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) gb[i] -= e[i] + g1[i];
-  // b = S m2, m2 = (M2x, M2y, 1)
-  const double gS = gb[0] * k.M2x + gb[1] * k.M2y + gb[2];
-  gM2x += gb[0] * S;
-  gM2y += gb[1] * S;
-  gc0 += gS;
-  gc1 += gS;
-  const double gc2 = gS;
-  // c = d1 x d2
-  double gd1[3] = {0, 0, 0}, gd2[3] = {0, 0, 0};
-  gd1[1] += gc0 * d2[2];
-  gd2[2] += gc0 * d1[1];
-  gd1[2] -= gc0 * d2[1];
-  gd2[1] -= gc0 * d1[2];
-  gd1[2] += gc1 * d2[0];
-  gd2[0] += gc1 * d1[2];
-  gd1[0] -= gc1 * d2[2];
-  gd2[2] -= gc1 * d1[0];
-  gd1[0] += gc2 * d2[1];
-  gd2[1] += gc2 * d1[0];
-  gd1[1] -= gc2 * d2[0];
-  gd2[0] -= gc2 * d1[1];
-  // d1 = (N2x, P2x, Q2x) - M2x, d2 likewise in y
-  gN2x += gd1[0];
-  gP2x += gd1[1];
-  gQ2x += gd1[2];
-  gM2x -= gd1[0] + gd1[1] + gd1[2];
-  gN2y += gd2[0];
-  gP2y += gd2[1];
-  gQ2y += gd2[2];
-  gM2y -= gd2[0] + gd2[1] + gd2[2];
-  // TL TR BR BL = M N Q P
-  gout[0] = gM2x;
-  gout[1] = gM2y;
-  gout[2] = gN2x;
-  gout[3] = gN2y;
-  gout[4] = gQ2x;
-  gout[5] = gQ2y;
-  gout[6] = gP2x;
-  gout[7] = gP2y;
-}
-
 __global__ void rect_bwd_kernel(const float *__restrict__ off, const double *__restrict__ gH, int B,
-                                double x0, double y0, double w, double r,
-                                float *__restrict__ goff) {
+                                RectArgs ra, float *__restrict__ goff) {
   const int bi = blockIdx.x * blockDim.x + threadIdx.x;
   if (bi >= B) return;
   double g[8];
-  rect_bwd_one(off + 8 * bi, gH + 9 * bi, x0, y0, w, r, g);
+  rect_h_vjp(off + 8 * bi, ra, gH + 9 * bi, g);
 #pragma unroll
   for (int i = 0; i < 8; ++i) goff[8 * bi + i] = static_cast<float>(g[i]);
 }
@@ -203,11 +142,13 @@ constexpr uint32_t kFarOffset = 0x80000000u;   // past every patch (h w <= 2^29 
 struct TapAddr {
   uint32_t o00, o01, o10, o11;   // byte offsets of taps (x0, y0), (x1, y0), (x0, y1), (x1, y1)
   bool x0in, x1in;               // tap columns inside the image
-  double ax, ay;                 // fractional position in the cell
+  float ax, ay;                  // fractional position in the cell
 };
 
+// Buffer over the P floats of one patch (P <= 2^29, so 4 P <= 2^31 bytes).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_buffer(const float *I, int P) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(I), 0, P * 4, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(I), 0, static_cast<int>(static_cast<uint32_t>(P) * 4u), 0x00020000);
 }
 
 __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
@@ -217,8 +158,8 @@ __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) 
   }
   const double fx = floor(sx), fy = floor(sy);
   TapAddr t;
-  t.ax = sx - fx;
-  t.ay = sy - fy;
+  t.ax = static_cast<float>(sx - fx);
+  t.ay = static_cast<float>(sy - fy);
   const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
   // cells with a tap inside the image; any other cell has all four taps outside
   const bool near = ix >= -1 && ix < w && iy >= -1 && iy < h;
@@ -247,34 +188,47 @@ __device__ __forceinline__ void tap_load(__amdgpu_buffer_rsrc_t r, const TapAddr
   L[3] = t.x1in ? v11 : 0.0f;
 }
 
+// Bilinear value and (GRAD) its derivatives in x and y inside the cell.
 struct Tap {
-  double v, dvdx, dvdy;
+  float v, dvdx, dvdy;
 };
 
 template <bool GRAD>
-__device__ __forceinline__ Tap tap_eval(const TapAddr &a, float L00, float L01, float L10,
-                                        float L11) {
-  const double I00 = static_cast<double>(L00), I01 = static_cast<double>(L01);
-  const double I10 = static_cast<double>(L10), I11 = static_cast<double>(L11);
-  const double top = fma(a.ax, I01 - I00, I00);
-  const double bot = fma(a.ax, I11 - I10, I10);
+__device__ __forceinline__ Tap tap_eval(const TapAddr &a, const float L[4]) {
+  const float d0 = L[1] - L[0], d1 = L[3] - L[2];
+  const float top = fmaf(a.ax, d0, L[0]);
+  const float bot = fmaf(a.ax, d1, L[2]);
+  const float dy = bot - top;
   Tap t;
-  t.v = fma(a.ay, bot - top, top);
-  t.dvdx = 0.0;
-  t.dvdy = 0.0;
+  t.v = fmaf(a.ay, dy, top);
+  t.dvdx = 0.0f;
+  t.dvdy = 0.0f;
   if (GRAD) {
-    t.dvdx = fma(a.ay, (I11 - I10) - (I01 - I00), I01 - I00);
-    t.dvdy = bot - top;
+    t.dvdx = fmaf(a.ay, d1 - d0, d0);
+    t.dvdy = dy;
   }
   return t;
 }
 
+// 1/q: a float reciprocal estimate and one double Newton step (relative error
+// ~2^-46; q outside the float range gives a non-finite position, which
+// samples as outside the image).
+__device__ __forceinline__ double recip(double q) {
+  const double r = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(q)));
+  return fma(fma(-q, r, 1.0), r, r);
+}
+
 // Pixels per thread per loop iteration (loads of all of them in flight at once).
 constexpr int kUnroll = 4;
+// Iterations between folds of the per-thread float partial sums into double.
+constexpr int kFold = 4;
 
-// Per-thread pixel walker (NT threads): pixel i = threadIdx.x + u * NT + k *
-// NT * kUnroll, with (x, y) advanced incrementally.
-template <int NT>
+// Per-thread pixels (NT threads): pixel i = threadIdx.x + u NT + k NT kUnroll.
+// ALIGNED (NT a multiple of w): all of a thread's pixels lie in one column
+// x = threadIdx.x % w, each kUnroll-step k advancing every row by NT kUnroll / w;
+// q = G (x, y, 1) is then a per-thread constant plus y G[:, 1] (3 FMAs).
+// Otherwise (x, y) is walked per pixel and q takes 6 FMAs.
+template <int NT, bool ALIGNED>
 struct PixelWalk {
   int x[kUnroll], y[kUnroll];
   int step_x, step_y, w;
@@ -292,11 +246,13 @@ struct PixelWalk {
   __device__ __forceinline__ void advance() {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      x[u] += step_x;
       y[u] += step_y;
-      if (x[u] >= w) {
-        x[u] -= w;
-        ++y[u];
+      if (!ALIGNED) {
+        x[u] += step_x;
+        if (x[u] >= w) {
+          x[u] -= w;
+          ++y[u];
+        }
       }
     }
   }
@@ -332,9 +288,7 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[N
 }
 
 // Per-patch G = 2^-e adj(H) shared by the workgroup, read back into scalar
-// registers (it is uniform): 18 fewer vector registers per lane, which lets
-// the backward kernels run 4 waves per SIMD (one 256-thread patch per SIMD
-// slot, all patches of a 1024-patch batch resident at once on 256 CUs).
+// registers (it is uniform).
 __device__ __forceinline__ void load_G(const double *H, double G[9], int &e) {
   __shared__ double Gs[9];
   __shared__ int es;
@@ -353,85 +307,6 @@ __device__ __forceinline__ void load_G(const double *H, double G[9], int &e) {
     G[i] = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
   }
   e = __builtin_amdgcn_readfirstlane(es);
-}
-
-// 1/q in double: a single-precision reciprocal estimate refined by two
-// Newton steps (relative error ~2^-52, no special-case handling needed since
-// G is power-of-two normalised; q outside the float range gives a non-finite
-// position, which samples as outside the image).
-__device__ __forceinline__ double recip(double q) {
-  double r = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(q)));
-  r = fma(fma(-q, r, 1.0), r, r);
-  r = fma(fma(-q, r, 1.0), r, r);
-  return r;
-}
-
-__device__ __forceinline__ void sample_pos(const double *G, double x, double y, double &sx,
-                                           double &sy, double &iq2) {
-  const double q0 = fma(G[0], x, fma(G[1], y, G[2]));
-  const double q1 = fma(G[3], x, fma(G[4], y, G[5]));
-  const double q2 = fma(G[6], x, fma(G[7], y, G[8]));
-  iq2 = recip(q2);
-  sx = q0 * iq2;
-  sy = q1 * iq2;
-}
-
-// One patch b per workgroup; Hb: its 9 entries of H (global or LDS).
-// MODE 0: loss only; 2: stored warp only (rounded to float).
-template <int MODE, int NT>
-__device__ __forceinline__ void warp_fwd_block(const double *Hb, const float *__restrict__ img,
-                                               const float *__restrict__ tgt, int h, int w, int b,
-                                               float *__restrict__ loss,
-                                               float *__restrict__ warped) {
-  double G[9];
-  int e;
-  load_G(Hb, G, e);
-  const int P = h * w;
-  const __amdgpu_buffer_rsrc_t rs = patch_buffer(img + static_cast<int64_t>(b) * P, P);
-  // the target as a buffer too: indices past the patch (the last loop's tail) read 0
-  const __amdgpu_buffer_rsrc_t rt = patch_buffer(MODE == 0 ? tgt + static_cast<int64_t>(b) * P
-                                                           : img, P);
-  double acc[1] = {0.0};
-  PixelWalk<NT> pw(w);
-  for (int i0 = threadIdx.x; i0 < P; i0 += NT * kUnroll) {
-    TapAddr ta[kUnroll];
-    float L[kUnroll][4], tv[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      double sx, sy, iq2;
-      sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx, sy, iq2);
-      ta[u] = tap_addr(sx, sy, h, w);
-      tap_load(rs, ta[u], L[u]);
-      if (MODE == 0)
-        tv[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-            rt, static_cast<uint32_t>(i0 + u * NT) * 4u, 0, 0));
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int i = i0 + u * NT;
-      if (i < P) {
-        const double v = tap_eval<false>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]).v;
-        if (MODE == 2) warped[static_cast<int64_t>(b) * P + i] = static_cast<float>(v);
-        if (MODE == 0) acc[0] += fabs(v - static_cast<double>(tv[u]));
-      }
-    }
-    pw.advance();
-  }
-  if (MODE == 0) {
-    double s[1];
-    block_sum<1, NT>(acc, s);
-    if (threadIdx.x == 0) loss[b] = static_cast<float>(s[0] / static_cast<double>(P));
-  }
-}
-
-template <int MODE, int NT>
-__global__ __launch_bounds__(NT) void warp_fwd_kernel(const double *__restrict__ H,
-                                                                const float *__restrict__ img,
-                                                                const float *__restrict__ tgt,
-                                                                int h, int w,
-                                                                float *__restrict__ loss,
-                                                                float *__restrict__ warped) {
-  warp_fwd_block<MODE, NT>(H + 9 * blockIdx.x, img, tgt, h, w, blockIdx.x, loss, warped);
 }
 
 // dL/dH from dL/dG (G = 2^-e adj(H)), thread 0, double precision.
@@ -455,111 +330,199 @@ __device__ __forceinline__ void adjugate_backward(const double *Hd, const double
   for (int i = 0; i < 9; ++i) gHout[i] = gH[i / 3][i % 3];
 }
 
-// One patch b per workgroup; Hb: its 9 entries of H (global or LDS); thread 0
-// writes dL/dH to gHout (9 doubles).
-// FROM_STORED = false: recompute r = I_w - T and use sign(r) gl, gl = grad_loss / (h w);
-// FROM_STORED = true: read dL/dI_w from grad_warped.
-template <bool FROM_STORED, int NT>
-__device__ __forceinline__ void warp_bwd_block(const double *Hb, const float *__restrict__ img,
-                                               const float *__restrict__ tgt, double gl,
-                                               const float *__restrict__ grad_warped, int h,
-                                               int w, int b, double *gHout) {
+// What a per-patch warp pass computes.
+enum WarpMode {
+  kLoss = 0,        // loss[b] = mean |I_w - T|
+  kGrad = 1,        // dL/dH from sign(r) gl, gl = grad_loss[b] / (h w) (recomputed r)
+  kStore = 2,       // warped image, rounded to float
+  kGradStored = 3,  // dL/dH from a stored dL/dI_w
+  kLossGrad = 4,    // loss[b] and dloss[b]/dH in one pass (gl = 1 / (h w))
+};
+
+// One patch b per workgroup; Hb: its 9 entries of H (global or LDS). Writes
+// the loss (kLoss, kLossGrad; thread 0), the warped image (kStore), and dL/dH
+// to gHout (kGrad, kGradStored, kLossGrad; thread 0, 9 doubles).
+// The gradient of the loss through q = G p, position (q0, q1) / q2: with
+// g = dL/dI_w at a pixel, (gx, gy) = g grad I there and iq = 1/q2,
+// dL/dG row 1 += gx iq p, row 2 += gy iq p, row 3 += -(gx sx + gy sy) iq p.
+template <int MODE, int NT, bool ALIGNED>
+__device__ __forceinline__ void warp_block(const double *Hb, const float *__restrict__ img,
+                                           const float *__restrict__ tgt, float gl, int h, int w,
+                                           int b, float *__restrict__ loss,
+                                           float *__restrict__ warped, double *gHout) {
+  constexpr bool GRAD = MODE == kGrad || MODE == kGradStored || MODE == kLossGrad;
+  constexpr bool LOSS = MODE == kLoss || MODE == kLossGrad;
   double G[9];
   int e;
   load_G(Hb, G, e);
   const int P = h * w;
   const __amdgpu_buffer_rsrc_t rs = patch_buffer(img + static_cast<int64_t>(b) * P, P);
-  const float *T = FROM_STORED ? grad_warped + static_cast<int64_t>(b) * P
-                               : tgt + static_cast<int64_t>(b) * P;
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  PixelWalk<NT> pw(w);
+  // the second stream (target or stored gradient) as a buffer too: indices
+  // past the patch (the last loop's tail) read 0
+  const float *T2 = MODE == kStore ? img : tgt;
+  const __amdgpu_buffer_rsrc_t rt = patch_buffer(T2 + static_cast<int64_t>(b) * P, P);
+  // float partial sums (folded every kFold iterations) and their double totals:
+  // 0..8 the dL/dG terms (ALIGNED: the x-multiplied ones without x), 9 the loss
+  constexpr int NS = 10;
+  float sf[NS];
+  double sd[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    sf[k] = 0.0f;
+    sd[k] = 0.0;
+  }
+  PixelWalk<NT, ALIGNED> pw(w);
+  // ALIGNED: per-thread constant part of q (column x)
+  double A[3] = {0.0, 0.0, 0.0};
+  const float xcol = static_cast<float>(pw.x[0]);
+  if (ALIGNED) {
+    const double xd = static_cast<double>(pw.x[0]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) A[r] = fma(G[3 * r], xd, G[3 * r + 2]);
+  }
+  auto fold = [&]() {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const double v = static_cast<double>(sf[k]);
+      sd[k] += (ALIGNED && (k == 0 || k == 3 || k == 6)) ? v * static_cast<double>(xcol) : v;
+      sf[k] = 0.0f;
+    }
+  };
+  int since = 0;
   for (int i0 = threadIdx.x; i0 < P; i0 += NT * kUnroll) {
     TapAddr ta[kUnroll];
-    double sx[kUnroll], sy[kUnroll], iq2[kUnroll];
-    float L[kUnroll][4], tv[kUnroll];
+    float L[kUnroll][4], tv[kUnroll], sxf[kUnroll], syf[kUnroll], iqf[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      sample_pos(G, static_cast<double>(pw.x[u]), static_cast<double>(pw.y[u]), sx[u], sy[u],
-                 iq2[u]);
-      ta[u] = tap_addr(sx[u], sy[u], h, w);
+      const double yd = static_cast<double>(pw.y[u]);
+      double q0, q1, q2;
+      if (ALIGNED) {
+        q0 = fma(G[1], yd, A[0]);
+        q1 = fma(G[4], yd, A[1]);
+        q2 = fma(G[7], yd, A[2]);
+      } else {
+        const double xd = static_cast<double>(pw.x[u]);
+        q0 = fma(G[0], xd, fma(G[1], yd, G[2]));
+        q1 = fma(G[3], xd, fma(G[4], yd, G[5]));
+        q2 = fma(G[6], xd, fma(G[7], yd, G[8]));
+      }
+      const double iq = recip(q2);
+      const double sx = q0 * iq, sy = q1 * iq;
+      ta[u] = tap_addr(sx, sy, h, w);
+      if (GRAD) {
+        sxf[u] = static_cast<float>(sx);
+        syf[u] = static_cast<float>(sy);
+        iqf[u] = static_cast<float>(iq);
+      }
       tap_load(rs, ta[u], L[u]);
-      tv[u] = T[min(i0 + u * NT, P - 1)];
+      if (MODE != kStore)
+        tv[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rt, static_cast<uint32_t>(i0 + u * NT) * 4u, 0, 0));
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (i0 + u * NT >= P) continue;
-      const Tap t = tap_eval<true>(ta[u], L[u][0], L[u][1], L[u][2], L[u][3]);
-      double g;
-      if (FROM_STORED) {
-        g = static_cast<double>(tv[u]);
-      } else {
-        const double r = t.v - static_cast<double>(tv[u]);
-        g = (r > 0.0) ? gl : ((r < 0.0) ? -gl : 0.0);
+      const int i = i0 + u * NT;
+      if (i < P) {
+        const Tap t = tap_eval<GRAD>(ta[u], L[u]);
+        if (MODE == kStore) warped[static_cast<int64_t>(b) * P + i] = t.v;
+        const float r = t.v - tv[u];
+        if (LOSS) sf[9] += fabsf(r);
+        if (GRAD) {
+          float g;
+          if (MODE == kGradStored)
+            g = tv[u];
+          else
+            g = r > 0.0f ? gl : (r < 0.0f ? -gl : 0.0f);
+          const float gx = g * t.dvdx, gy = g * t.dvdy;
+          const float a0 = gx * iqf[u], a1 = gy * iqf[u];
+          const float a2 = -fmaf(gx, sxf[u], gy * syf[u]) * iqf[u];
+          const float yf = static_cast<float>(pw.y[u]);
+          if (ALIGNED) {
+            sf[0] += a0;
+            sf[3] += a1;
+            sf[6] += a2;
+          } else {
+            const float xf = static_cast<float>(pw.x[u]);
+            sf[0] = fmaf(a0, xf, sf[0]);
+            sf[3] = fmaf(a1, xf, sf[3]);
+            sf[6] = fmaf(a2, xf, sf[6]);
+          }
+          sf[1] = fmaf(a0, yf, sf[1]);
+          sf[2] += a0;
+          sf[4] = fmaf(a1, yf, sf[4]);
+          sf[5] += a1;
+          sf[7] = fmaf(a2, yf, sf[7]);
+          sf[8] += a2;
+        }
       }
-      const double xf = static_cast<double>(pw.x[u]), yf = static_cast<double>(pw.y[u]);
-      const double gx = g * t.dvdx, gy = g * t.dvdy;
-      const double a0 = gx * iq2[u], a1 = gy * iq2[u];
-      const double a2 = -(gx * sx[u] + gy * sy[u]) * iq2[u];
-      acc[0] = fma(a0, xf, acc[0]);
-      acc[1] = fma(a0, yf, acc[1]);
-      acc[2] += a0;
-      acc[3] = fma(a1, xf, acc[3]);
-      acc[4] = fma(a1, yf, acc[4]);
-      acc[5] += a1;
-      acc[6] = fma(a2, xf, acc[6]);
-      acc[7] = fma(a2, yf, acc[7]);
-      acc[8] += a2;
     }
     pw.advance();
+    if (++since == kFold) {
+      fold();
+      since = 0;
+    }
   }
-  double gG[9];
-  block_sum<9, NT>(acc, gG);
-  if (threadIdx.x == 0) adjugate_backward(Hb, gG, e, gHout);
+  fold();
+  if (LOSS && !GRAD) {
+    double s1[1] = {sd[9]}, o1[1];
+    block_sum<1, NT>(s1, o1);
+    if (threadIdx.x == 0) loss[b] = static_cast<float>(o1[0] / static_cast<double>(P));
+  }
+  if (GRAD) {
+    double s10[NS], o10[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s10[k] = sd[k];
+    block_sum<NS, NT>(s10, o10);
+    if (threadIdx.x == 0) {
+      if (LOSS) loss[b] = static_cast<float>(o10[9] / static_cast<double>(P));
+      adjugate_backward(Hb, o10, e, gHout);
+    }
+  }
 }
 
-template <bool FROM_STORED, int NT>
-__global__ __launch_bounds__(NT) void warp_bwd_kernel(
-    const double *__restrict__ H, const float *__restrict__ img, const float *__restrict__ tgt,
-    const float *__restrict__ grad_loss, const float *__restrict__ grad_warped, int h, int w,
-    double *__restrict__ grad_H) {
+template <int MODE, int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void warp_kernel(const double *__restrict__ H,
+                                                  const float *__restrict__ img,
+                                                  const float *__restrict__ tgt,
+                                                  const float *__restrict__ grad_loss, int h,
+                                                  int w, float *__restrict__ loss,
+                                                  float *__restrict__ warped,
+                                                  double *__restrict__ grad_H) {
   const int b = blockIdx.x;
-  const double gl =
-      FROM_STORED ? 0.0 : static_cast<double>(grad_loss[b]) / static_cast<double>(h * w);
-  warp_bwd_block<FROM_STORED, NT>(H + 9 * b, img, tgt, gl, grad_warped, h, w, b, grad_H + 9 * b);
+  const float gl = MODE == kGrad ? static_cast<float>(static_cast<double>(grad_loss[b]) /
+                                                      static_cast<double>(h * w))
+                                 : 0.0f;
+  warp_block<MODE, NT, ALIGNED>(H + 9 * b, img, tgt, gl, h, w, b, loss, warped, grad_H + 9 * b);
 }
 
-// ---- fused offsets -> loss and offsets -> gradient (one workgroup per patch) --
-// Algorithm 1 runs in thread 0 of the patch's workgroup into LDS, then the
-// warp; the backward also runs Algorithm 1's reverse mode in thread 0. The
-// arithmetic is that of the separate kernels, in the same order.
-struct RectArgs {
-  double x0, y0, w, r;
-};
-
+// ---- fused offsets -> loss / gradient (one workgroup per patch) -------------
+// ACA with the rectangle's source corners runs in thread 0 of the patch's
+// workgroup into LDS, then the warp; gradients go back through ACA's reverse
+// mode in thread 0. The arithmetic is that of the separate kernels.
 __device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, double *Hs) {
   if (threadIdx.x == 0) {
     double hh[9];
-    rect_aca(rect_targets(o, ra.x0, ra.y0, ra.w, ra.r), ra.x0, ra.y0, ra.w, ra.r, hh);
+    rect_h(o, ra, hh);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Hs[i] = hh[i];
   }
   __syncthreads();
 }
 
-template <int NT>
+template <int NT, bool ALIGNED>
 __global__ __launch_bounds__(NT) void photo_fwd_kernel(const float *__restrict__ off,
-                                                                 const float *__restrict__ img,
-                                                                 const float *__restrict__ tgt,
-                                                                 int h, int w, RectArgs ra,
-                                                                 float *__restrict__ loss) {
+                                                       const float *__restrict__ img,
+                                                       const float *__restrict__ tgt, int h,
+                                                       int w, RectArgs ra,
+                                                       float *__restrict__ loss) {
   __shared__ double Hs[9];
   rect_to_lds(off + 8 * blockIdx.x, ra, Hs);
-  warp_fwd_block<0, NT>(Hs, img, tgt, h, w, blockIdx.x, loss, nullptr);
+  warp_block<kLoss, NT, ALIGNED>(Hs, img, tgt, 0.0f, h, w, blockIdx.x, loss, nullptr, nullptr);
 }
 
 // grad_offsets = grad_loss[b] dL_b/d offsets_b; with STEP, instead
 // offsets_b -= step * float(dL_b/d offsets_b) in place (grad_loss = 1).
-template <bool STEP, int NT>
+template <bool STEP, int NT, bool ALIGNED>
 __global__ __launch_bounds__(NT) void photo_bwd_kernel(
     float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ grad_loss, int h, int w, RectArgs ra, float step,
@@ -568,11 +531,12 @@ __global__ __launch_bounds__(NT) void photo_bwd_kernel(
   __shared__ double gHs[9];
   const int b = blockIdx.x;
   rect_to_lds(off + 8 * b, ra, Hs);
-  const double gl = static_cast<double>(STEP ? 1.0f : grad_loss[b]) / static_cast<double>(h * w);
-  warp_bwd_block<false, NT>(Hs, img, tgt, gl, nullptr, h, w, b, gHs);
+  const float gl = static_cast<float>(static_cast<double>(STEP ? 1.0f : grad_loss[b]) /
+                                      static_cast<double>(h * w));
+  warp_block<kGrad, NT, ALIGNED>(Hs, img, tgt, gl, h, w, b, nullptr, nullptr, gHs);
   if (threadIdx.x == 0) {
     double g[8];
-    rect_bwd_one(off + 8 * b, gHs, ra.x0, ra.y0, ra.w, ra.r, g);
+    rect_h_vjp(off + 8 * b, ra, gHs, g);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const float gf = static_cast<float>(g[i]);
@@ -582,6 +546,34 @@ __global__ __launch_bounds__(NT) void photo_bwd_kernel(
         goff[8 * b + i] = gf;
     }
   }
+}
+
+// Loss and its gradient in one pass over img and tgt: loss[b] and
+// grad_unit[b] = dloss[b]/d offsets_b (grad_loss = 1).
+template <int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void photo_fwd_grad_kernel(
+    const float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
+    int h, int w, RectArgs ra, float *__restrict__ loss, float *__restrict__ grad_unit) {
+  __shared__ double Hs[9];
+  __shared__ double gHs[9];
+  const int b = blockIdx.x;
+  rect_to_lds(off + 8 * b, ra, Hs);
+  const float gl = static_cast<float>(1.0 / static_cast<double>(h * w));
+  warp_block<kLossGrad, NT, ALIGNED>(Hs, img, tgt, gl, h, w, b, loss, nullptr, gHs);
+  if (threadIdx.x == 0) {
+    double g[8];
+    rect_h_vjp(off + 8 * b, ra, gHs, g);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) grad_unit[8 * b + i] = static_cast<float>(g[i]);
+  }
+}
+
+// out[b, k] = grad_loss[b] * grad_unit[b, k] (8 per patch).
+__global__ void scale_grad_kernel(const float *__restrict__ grad_unit,
+                                  const float *__restrict__ grad_loss, int B,
+                                  float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 8 * B) out[i] = grad_loss[i / 8] * grad_unit[i];
 }
 
 __global__ void l1_fwd_kernel(const float *__restrict__ warped, const float *__restrict__ tgt,
@@ -662,7 +654,7 @@ __global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__res
 // Iterative refinement of the offsets (the six-solve structure of iterative
 // deep homography networks, with the network's predicted update replaced by a
 // gradient step on the photometric loss): per iteration one fused launch runs
-// Algorithm 1, the warp + L1 backward, Algorithm 1's reverse mode and
+// ACA with the rectangle's source corners, the warp + L1 backward, ACA's reverse mode and
 // off -= step * grad for every patch.
 struct RefineArgs {
   const float *img, *tgt;
@@ -692,37 +684,48 @@ static int diff_threads(int B, int max_nt, int waves) {
   return std::min(nt, max_nt);
 }
 
+// Launch shape of a per-patch kernel: f(NT, ALIGNED) with NT from
+// diff_threads and ALIGNED = (NT is a multiple of the patch width w).
 template <int MAXNT = 1024, int WAVES = 8192, typename F>
-static void with_threads(int B, F &&f) {
+static void with_shape(int B, int w, F &&f) {
   const int nt = diff_threads(B, MAXNT, WAVES);
+  const bool al = nt % w == 0;
+  auto go = [&](auto NTc) {
+    if (al)
+      f(NTc, std::true_type());
+    else
+      f(NTc, std::false_type());
+  };
   if constexpr (MAXNT >= 1024) {
     if (nt == 1024) {
-      f(std::integral_constant<int, 1024>());
+      go(std::integral_constant<int, 1024>());
       return;
     }
   }
   if (nt == 512) {
-    f(std::integral_constant<int, 512>());
+    go(std::integral_constant<int, 512>());
     return;
   }
-  f(std::integral_constant<int, 256>());
+  go(std::integral_constant<int, 256>());
 }
 
 static int launch_refine(const RefineArgs &a, hipStream_t s) {
   const RectArgs ra = patch_rect(a.h, a.w);
   for (int it = 0; it < a.iters; ++it) {
-    with_threads<512, 4096>(a.B, [&](auto nt) {
+    with_shape<512, 4096>(a.B, a.w, [&](auto nt, auto al) {
       constexpr int NT = decltype(nt)::value;
-      hipLaunchKernelGGL((photo_bwd_kernel<true, NT>), dim3(a.B), dim3(NT), 0, s, a.off, a.img,
-                         a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
+      constexpr bool AL = decltype(al)::value;
+      hipLaunchKernelGGL((photo_bwd_kernel<true, NT, AL>), dim3(a.B), dim3(NT), 0, s, a.off,
+                         a.img, a.tgt, nullptr, a.h, a.w, ra, a.step, nullptr);
     });
     if (int st = launched("photo_bwd_kernel<step>")) return st;
   }
   if (a.loss) {
-    with_threads(a.B, [&](auto nt) {
+    with_shape(a.B, a.w, [&](auto nt, auto al) {
       constexpr int NT = decltype(nt)::value;
-      hipLaunchKernelGGL((photo_fwd_kernel<NT>), dim3(a.B), dim3(NT), 0, s, a.off, a.img, a.tgt,
-                         a.h, a.w, ra, a.loss);
+      constexpr bool AL = decltype(al)::value;
+      hipLaunchKernelGGL((photo_fwd_kernel<NT, AL>), dim3(a.B), dim3(NT), 0, s, a.off, a.img,
+                         a.tgt, a.h, a.w, ra, a.loss);
     });
     if (int st = launched("photo_fwd_kernel")) return st;
   }
@@ -769,9 +772,10 @@ extern "C" int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float 
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && H, "hg_aca_rect_fwd: NULL pointer");
   HG_REQUIRE(std::isfinite(x0) && std::isfinite(y0), "hg_aca_rect_fwd: non-finite origin");
+  const RectArgs ra = {static_cast<double>(x0), static_cast<double>(y0), static_cast<double>(w),
+                       static_cast<double>(r)};
   hipLaunchKernelGGL(rect_fwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream),
-                     offsets, B, static_cast<double>(x0), static_cast<double>(y0),
-                     static_cast<double>(w), static_cast<double>(r), H);
+                     offsets, B, ra, H);
   return launched("rect_fwd_kernel");
 }
 
@@ -782,9 +786,10 @@ extern "C" int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && grad_H && grad_offsets, "hg_aca_rect_bwd: NULL pointer");
   HG_REQUIRE(std::isfinite(x0) && std::isfinite(y0), "hg_aca_rect_bwd: non-finite origin");
+  const RectArgs ra = {static_cast<double>(x0), static_cast<double>(y0), static_cast<double>(w),
+                       static_cast<double>(r)};
   hipLaunchKernelGGL(rect_bwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream),
-                     offsets, grad_H, B, static_cast<double>(x0), static_cast<double>(y0),
-                     static_cast<double>(w), static_cast<double>(r), grad_offsets);
+                     offsets, grad_H, B, ra, grad_offsets);
   return launched("rect_bwd_kernel");
 }
 
@@ -817,12 +822,13 @@ extern "C" int hg_warp_l1_fwd(const double *H, const float *img, const float *tg
   if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_fwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && loss, "hg_warp_l1_fwd: NULL pointer");
-  with_threads(B, [&](auto nt) {
+  with_shape(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((warp_fwd_kernel<0, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H, img,
-                       tgt, h, w, loss, nullptr);
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((warp_kernel<kLoss, NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream), H,
+                       img, tgt, nullptr, h, w, loss, nullptr, nullptr);
   });
-  return launched("warp_fwd_kernel");
+  return launched("warp_kernel<loss>");
 }
 
 extern "C" int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt,
@@ -832,12 +838,13 @@ extern "C" int hg_warp_l1_bwd(const double *H, const float *img, const float *tg
   if (int st = check_img(img, tgt, B, h, w, "hg_warp_l1_bwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_loss && grad_H, "hg_warp_l1_bwd: NULL pointer");
-  with_threads<512, 4096>(B, [&](auto nt) {
+  with_shape<512, 4096>(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((warp_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
-                       img, tgt, grad_loss, nullptr, h, w, grad_H);
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((warp_kernel<kGrad, NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream), H,
+                       img, tgt, grad_loss, h, w, nullptr, nullptr, grad_H);
   });
-  return launched("warp_bwd_kernel");
+  return launched("warp_kernel<grad>");
 }
 
 extern "C" int hg_warp_store_fwd(const double *H, const float *img, int32_t B, int32_t h,
@@ -846,12 +853,13 @@ extern "C" int hg_warp_store_fwd(const double *H, const float *img, int32_t B, i
   if (int st = check_img(img, warped, B, h, w, "hg_warp_store_fwd")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H, "hg_warp_store_fwd: NULL H");
-  with_threads(B, [&](auto nt) {
+  with_shape(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((warp_fwd_kernel<2, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H, img,
-                       nullptr, h, w, nullptr, warped);
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((warp_kernel<kStore, NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream), H,
+                       img, nullptr, nullptr, h, w, nullptr, warped, nullptr);
   });
-  return launched("warp_fwd_kernel<store>");
+  return launched("warp_kernel<store>");
 }
 
 extern "C" int hg_l1_fwd(const float *warped, const float *tgt, int32_t B, int32_t h, int32_t w,
@@ -883,12 +891,14 @@ extern "C" int hg_warp_bwd_from_grad(const double *H, const float *img, const fl
   if (int st = check_img(img, grad_warped, B, h, w, "hg_warp_bwd_from_grad")) return st;
   if (B == 0) return HG_OK;
   HG_REQUIRE(H && grad_H, "hg_warp_bwd_from_grad: NULL pointer");
-  with_threads<512, 4096>(B, [&](auto nt) {
+  with_shape<512, 4096>(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((warp_bwd_kernel<true, NT>), dim3(B), dim3(NT), 0, as_stream(stream), H,
-                       img, nullptr, nullptr, grad_warped, h, w, grad_H);
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((warp_kernel<kGradStored, NT, AL>), dim3(B), dim3(NT), 0,
+                       as_stream(stream), H, img, grad_warped, nullptr, h, w, nullptr, nullptr,
+                       grad_H);
   });
-  return launched("warp_bwd_kernel<stored>");
+  return launched("warp_kernel<grad_stored>");
 }
 
 extern "C" int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt,
@@ -898,10 +908,11 @@ extern "C" int hg_photometric_fwd(const float *offsets, const float *img, const 
   HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_fwd: patches need h, w >= 2");
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && loss, "hg_photometric_fwd: NULL offsets or loss");
-  with_threads(B, [&](auto nt) {
+  with_shape(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((photo_fwd_kernel<NT>), dim3(B), dim3(NT), 0, as_stream(stream), offsets,
-                       img, tgt, h, w, patch_rect(h, w), loss);
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((photo_fwd_kernel<NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream),
+                       offsets, img, tgt, h, w, patch_rect(h, w), loss);
   });
   return launched("photo_fwd_kernel");
 }
@@ -914,13 +925,43 @@ extern "C" int hg_photometric_bwd(const float *offsets, const float *img, const 
   HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_bwd: patches need h, w >= 2");
   if (B == 0) return HG_OK;
   HG_REQUIRE(offsets && grad_loss && grad_offsets, "hg_photometric_bwd: NULL pointer");
-  with_threads<512, 4096>(B, [&](auto nt) {
+  with_shape<512, 4096>(B, w, [&](auto nt, auto al) {
     constexpr int NT = decltype(nt)::value;
-    hipLaunchKernelGGL((photo_bwd_kernel<false, NT>), dim3(B), dim3(NT), 0, as_stream(stream),
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((photo_bwd_kernel<false, NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream),
                        const_cast<float *>(offsets), img, tgt, grad_loss, h, w, patch_rect(h, w),
                        0.0f, grad_offsets);
   });
   return launched("photo_bwd_kernel");
+}
+
+extern "C" int hg_photometric_fwd_grad(const float *offsets, const float *img, const float *tgt,
+                                       int32_t B, int32_t h, int32_t w, float *loss,
+                                       float *grad_unit, void *stream) {
+  clear_error();
+  if (int st = check_img(img, tgt, B, h, w, "hg_photometric_fwd_grad")) return st;
+  HG_REQUIRE(h >= 2 && w >= 2, "hg_photometric_fwd_grad: patches need h, w >= 2");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(offsets && loss && grad_unit, "hg_photometric_fwd_grad: NULL pointer");
+  with_shape<512, 4096>(B, w, [&](auto nt, auto al) {
+    constexpr int NT = decltype(nt)::value;
+    constexpr bool AL = decltype(al)::value;
+    hipLaunchKernelGGL((photo_fwd_grad_kernel<NT, AL>), dim3(B), dim3(NT), 0, as_stream(stream),
+                       offsets, img, tgt, h, w, patch_rect(h, w), loss, grad_unit);
+  });
+  return launched("photo_fwd_grad_kernel");
+}
+
+extern "C" int hg_scale_grad(const float *grad_unit, const float *grad_loss, int32_t B,
+                             float *grad_offsets, void *stream) {
+  clear_error();
+  HG_REQUIRE(B >= 0, "hg_scale_grad: B < 0");
+  if (B == 0) return HG_OK;
+  HG_REQUIRE(grad_unit && grad_loss && grad_offsets, "hg_scale_grad: NULL pointer");
+  HG_REQUIRE(B <= (1 << 27), "hg_scale_grad: B too large");
+  hipLaunchKernelGGL(scale_grad_kernel, dim3((8 * B + 255) / 256), dim3(256), 0,
+                     as_stream(stream), grad_unit, grad_loss, B, grad_offsets);
+  return launched("scale_grad_kernel");
 }
 
 extern "C" int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,

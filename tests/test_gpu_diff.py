@@ -1,16 +1,19 @@
 """Differentiable 4-point-offset pipeline on the GPU against the float64 oracle.
 
-Every per-patch and per-pixel step runs in double precision on the float
-inputs, so the bars are those of float64 arithmetic: H from Algorithm 1
-within 1e-12 (Frobenius-normalised) of the oracle's; its vector-Jacobian
-product within 1e-10 relative; per-patch loss within 1e-6 relative (the loss
-is returned as float); the per-patch gradient with respect to the 8 offsets
-within GRAD_TOL relative (norm-wise) of float64 autograd through the DLT
-solve. Float64 central finite differences (h = 1e-6) agree within FD_TOL: a
-step of 1e-6 moves a few pixels across the kinks of the bilinear sampler. The
-stored-intermediate form rounds the warped image to float, so it agrees with
-the recompute form within 1e-5 (a pixel whose residual is within a float ulp
-of 0 can change sign)."""
+Per-patch steps (H, G = adj H, the sample position and the floor that picks
+the bilinear cell) are double precision; the per-pixel terms after the floor
+(bilinear weights, taps, residual, gradient terms) are float with double
+per-patch sums. Bars: H within 1e-12 (Frobenius-normalised) of the oracle's;
+its vector-Jacobian product within 1e-6 relative (float output); per-patch
+loss within 1e-6 relative; the per-patch gradient with respect to the 8
+offsets within GRAD_TOL = 1e-4 relative (norm-wise) of float64 autograd
+through the DLT solve (float sums over h w terms with sign cancellation), the
+error distribution printed. Float64 central finite differences (h = 1e-6)
+agree within FD_TOL. The single-pass (loss and gradient together),
+recomputing and separate-stage forms agree within 1e-6 (loss) and 1e-5
+(gradient: their sums run in different orders); the
+stored-intermediate form rounds nothing that the others do not, and agrees
+within 1e-5."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +24,7 @@ from oracle import warp as ow
 from tests.gpu_util import announce, require_gpu
 
 pytestmark = pytest.mark.gpu
-GRAD_TOL = 1e-6
+GRAD_TOL = 1e-4
 FD_TOL = 1e-4
 
 
@@ -31,23 +34,53 @@ def rel(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
+def rect_src_dst(off, x0, y0, w, r):
+    """Source (M N P Q = TL TR BL BR) of the rectangle and the targets
+    corners + offsets (offset order TL TR BR BL), as (B, 8) float64."""
+    s = np.array(hg.rect_corners(x0, y0, w, r), np.float64)   # M N P Q
+    o = off.astype(np.float64).reshape(-1, 4, 2)[:, [0, 1, 3, 2], :].reshape(-1, 8)
+    return np.broadcast_to(s, o.shape).copy(), s[None] + o
+
+
 def test_rect_forward_backward():
+    """The rectangle H is ACA's with the rectangle's source corners: raw
+    values within 1e-12 of the oracle's general ACA, equal up to scale to
+    Algorithm 1 and to the exact solution; its vector-Jacobian product is the
+    oracle's (float64 autograd through general ACA and through Algorithm 1)."""
     require_gpu()
     import paper_2402_18008_amd as hgpu
     rng = np.random.default_rng(0)
     off = rng.uniform(-32, 32, (300, 4, 2)).astype(np.float32)
     announce("aca_rect fwd/bwd B=300")
     H = hgpu.hg_aca_rect_fwd(torch.from_numpy(off).cuda(), 0.0, 0.0, 127.0, 1.0).cpu().numpy()
+    src, dst = rect_src_dst(off, 0.0, 0.0, 127.0, 1.0)
+    d64 = torch.from_numpy(dst).requires_grad_(True)
+    Ha = ow.h_aca(torch.from_numpy(src), d64)
+    assert np.abs(H.reshape(-1, 3, 3) - Ha.detach().numpy()).max() / np.abs(Ha.detach().numpy()).max() < 1e-12
     o64 = torch.from_numpy(off.astype(np.float64)).requires_grad_(True)
     Hr = ow.h_rect(o64, 128)
     assert hg.herr(H.reshape(-1, 3, 3), Hr.detach().numpy()).max() < 1e-12
-    # raw (unscaled) values are the algorithm's polynomials
-    assert np.abs(H.reshape(-1, 3, 3) - Hr.detach().numpy()).max() / np.abs(Hr.detach().numpy()).max() < 1e-12
     gH = rng.normal(size=(300, 9))
     g = hgpu.hg_aca_rect_bwd(torch.from_numpy(off).cuda(), torch.from_numpy(gH).cuda(), 0.0, 0.0,
                              127.0, 1.0).cpu().numpy()
-    (gr,) = torch.autograd.grad((Hr * torch.from_numpy(gH).reshape(-1, 3, 3)).sum(), o64)
-    assert rel(g, gr.numpy()).max() < 1e-6     # float output
+    (gd,) = torch.autograd.grad((Ha * torch.from_numpy(gH).reshape(-1, 3, 3)).sum(), d64,
+                                retain_graph=True)
+    gref = gd.numpy().reshape(-1, 4, 2)[:, [0, 1, 3, 2], :]      # back to TL TR BR BL
+    assert rel(g, gref).max() < 1e-6     # float output
+    # the same direction through Algorithm 1: H differs by a per-patch scale
+    # s(offsets), so grad_H projected orthogonally to H gives equal products
+    Hn = Ha.detach().numpy().reshape(-1, 9)
+    Hn = Hn / np.linalg.norm(Hn, axis=1, keepdims=True)
+    gperp = gH - (gH * Hn).sum(1, keepdims=True) * Hn
+    gp = hgpu.hg_aca_rect_bwd(torch.from_numpy(off).cuda(), torch.from_numpy(gperp).cuda(), 0.0,
+                              0.0, 127.0, 1.0).cpu().numpy()
+    Ha_n = Ha / Ha.reshape(-1, 9).norm(dim=1)[:, None, None]
+    Hr_n = Hr / Hr.reshape(-1, 9).norm(dim=1)[:, None, None] * torch.sign(
+        (Hr * Ha).reshape(-1, 9).sum(1))[:, None, None]
+    (ga,) = torch.autograd.grad((Ha_n * torch.from_numpy(gperp).reshape(-1, 3, 3)).sum(), d64)
+    (gr,) = torch.autograd.grad((Hr_n * torch.from_numpy(gperp).reshape(-1, 3, 3)).sum(), o64)
+    ga = ga.numpy().reshape(-1, 4, 2)[:, [0, 1, 3, 2], :]
+    assert rel(ga, gr.numpy()).max() < 1e-9      # normalised H: same function of offsets
     # a general rectangle (x0, y0, w, r)
     x0, y0, w, r = 3.0, -2.0, 50.0, 1.25
     H = hgpu.hg_aca_rect_fwd(torch.from_numpy(off).cuda(), x0, y0, w, r).cpu().numpy()
@@ -83,7 +116,7 @@ def compare_oracle(pb, L, g, idx, label):
     return el, eg
 
 
-@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("fused", [True, "recompute", False])
 def test_small_patches_against_oracle(fused):
     require_gpu()
     pb = synth.patches(24, 21, size=64, sigma=3.0, max_shift=8, max_offset=12.0)
@@ -134,7 +167,8 @@ def test_ragged_sizes_and_stored_form():
     # against the oracle's warp of the same H
     Hd = H.cpu().reshape(B, 3, 3)
     Wr = ow.warp(img.double().cpu(), Hd)
-    assert (Wr - Wp.double().cpu()).abs().max() < 1e-6
+    # (float bilinear evaluation: a few float ulps of values up to ~5)
+    assert (Wr - Wp.double().cpu()).abs().max() < 4e-6
     # and the whole pipeline against the oracle's autograd
     pbl = type("PB", (), {})()
     pbl.offsets, pbl.img, pbl.tgt = off.cpu().numpy(), img.cpu().numpy(), tgt.cpu().numpy()
@@ -150,16 +184,25 @@ def test_ragged_sizes_and_stored_form():
 
 
 def test_config4_full_batch_sampled():
-    """B = 1024 patches of 128 x 128 in one call; 32 sampled patches against the
-    float64 oracle."""
+    """B = 1024 patches of 128 x 128 in one call (single-pass and recomputing
+    forms); 32 sampled patches against float64 autograd through the DLT solve
+    and 4 against float64 central finite differences."""
     require_gpu()
     announce("warp-l1 config4 B=1024 generating")
     pb = synth.config4()
     announce("warp-l1 config4 fwd+bwd")
     L, g = run_pipeline(pb)
+    Lr, gr = run_pipeline(pb, fused="recompute")
     assert np.isfinite(L).all() and np.isfinite(g).all()
+    # (the two forms run with different workgroup sizes, so their sums differ in order)
+    assert np.allclose(L, Lr, rtol=1e-6, atol=0) and rel(g, gr).max() < 1e-6
     idx = np.random.default_rng(1).choice(1024, 32, replace=False)
     compare_oracle(pb, L[idx], g[idx], idx, "config4")
+    fd_idx = idx[:4]
+    fd = ow.loss_fd_grad(pb.offsets[fd_idx], pb.img[fd_idx], pb.tgt[fd_idx], h=1e-6).numpy()
+    efd = rel(g[fd_idx], fd)
+    print("config4 finite differences: rel err", efd)
+    assert efd.max() < FD_TOL
 
 
 @pytest.mark.parametrize("B", [1, 3, 257, 1000])
@@ -265,9 +308,11 @@ def test_refine_against_oracle_and_graph_replays():
 
 
 def test_fused_pipeline_equals_separate_stages():
-    """The fused offsets -> loss / gradient launches do the arithmetic of the
-    separate Algorithm 1, warp and reverse-mode kernels in the same order: the
-    results are identical, on square and non-square patches."""
+    """The recomputing fused launches do the arithmetic of the separate ACA,
+    warp and reverse-mode kernels in the same order: the results are
+    identical, on square and non-square patches. The single-pass form (its
+    own launch shape and sum order; the gradient scaled by grad_loss after
+    the pass) agrees within 1e-6 (loss) and 1e-5 (gradient)."""
     require_gpu()
     for B, h, w, seed in ((64, 128, 128, 4), (7, 37, 53, 5)):
         rng = np.random.default_rng(seed)
@@ -276,7 +321,7 @@ def test_fused_pipeline_equals_separate_stages():
         o = rng.uniform(-8, 8, (B, 4, 2)).astype(np.float32)
         announce(f"fused vs separate B={B} {h}x{w}")
         res = []
-        for fused in (True, False):
+        for fused in ("recompute", False, True):
             off = torch.from_numpy(o).cuda().requires_grad_(True)
             import paper_2402_18008_amd as hgpu
             L = hgpu.photometric_loss(off, img, tgt, fused=fused)
@@ -286,3 +331,5 @@ def test_fused_pipeline_equals_separate_stages():
             res.append((L.detach().cpu(), g.cpu(), gl))
         assert torch.equal(res[0][0], res[1][0])
         assert torch.equal(res[0][1], res[1][1])
+        assert torch.allclose(res[2][0], res[0][0], rtol=1e-6, atol=0)
+        assert rel(res[2][1].numpy(), res[0][1].numpy()).max() < 1e-5

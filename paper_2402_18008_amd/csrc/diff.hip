@@ -135,13 +135,16 @@ __device__ __forceinline__ int adjugate_scaled(const double *Hd, double G[9]) {
 // before using any of them. The patch image is read as a raw buffer of its
 // h w floats, whose loads return 0 at byte offsets past its end (the hardware's
 // range check): a row above the image gets an offset past the end, a row below
-// it lies past the end already, and the two tap columns are clamped into the
-// image and masked. Offsets are 32-bit and never negative.
+// it lies past the end already. Each row of the cell is one 8-byte load of
+// two adjacent columns starting at cp = clamp(x0, 0, w - 2), from which the
+// taps x0 and x0 + 1 are picked, and masked where they lie outside the image.
+// Offsets are 32-bit and never negative.
 constexpr uint32_t kFarOffset = 0x80000000u;   // past every patch (h w <= 2^29 floats)
 
 struct TapAddr {
-  uint32_t o00, o01, o10, o11;   // byte offsets of taps (x0, y0), (x1, y0), (x0, y1), (x1, y1)
+  uint32_t o0, o1;               // byte offsets of the column pair in rows y0, y0 + 1
   bool x0in, x1in;               // tap columns inside the image
+  bool x0hi, x1lo;               // tap x0 is the pair's second column / x0 + 1 its first
   float ax, ay;                  // fractional position in the cell
 };
 
@@ -165,27 +168,27 @@ __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) 
   const bool near = ix >= -1 && ix < w && iy >= -1 && iy < h;
   const uint32_t row0 = near && iy >= 0 ? static_cast<uint32_t>(iy * w) * 4u : kFarOffset;
   const uint32_t row1 = near ? static_cast<uint32_t>((iy + 1) * w) * 4u : kFarOffset;
-  const uint32_t c0 = static_cast<uint32_t>(max(ix, 0)) * 4u;
-  const uint32_t c1 = static_cast<uint32_t>(min(ix + 1, w - 1)) * 4u;
-  t.o00 = row0 + c0;
-  t.o01 = row0 + c1;
-  t.o10 = row1 + c0;
-  t.o11 = row1 + c1;
+  const int cp = max(min(ix, w - 2), 0);
+  t.o0 = row0 + static_cast<uint32_t>(cp) * 4u;
+  t.o1 = row1 + static_cast<uint32_t>(cp) * 4u;
   t.x0in = ix >= 0;
   t.x1in = ix + 1 < w;
+  t.x0hi = ix != cp;
+  t.x1lo = ix + 1 == cp;
   return t;
 }
 
-// The four taps of a cell (column-masked; rows outside read 0).
+// The four taps of a cell (x0 y0, x1 y0, x0 y1, x1 y1; column-masked, rows
+// outside read 0).
 __device__ __forceinline__ void tap_load(__amdgpu_buffer_rsrc_t r, const TapAddr &t, float L[4]) {
-  const float v00 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o00, 0, 0));
-  const float v01 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o01, 0, 0));
-  const float v10 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o10, 0, 0));
-  const float v11 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, t.o11, 0, 0));
-  L[0] = t.x0in ? v00 : 0.0f;
-  L[1] = t.x1in ? v01 : 0.0f;
-  L[2] = t.x0in ? v10 : 0.0f;
-  L[3] = t.x1in ? v11 : 0.0f;
+  const auto p0 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o0, 0, 0);
+  const auto p1 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o1, 0, 0);
+  const float a0 = __uint_as_float(p0[0]), b0 = __uint_as_float(p0[1]);
+  const float a1 = __uint_as_float(p1[0]), b1 = __uint_as_float(p1[1]);
+  L[0] = t.x0in ? (t.x0hi ? b0 : a0) : 0.0f;
+  L[1] = t.x1in ? (t.x1lo ? a0 : b0) : 0.0f;
+  L[2] = t.x0in ? (t.x0hi ? b1 : a1) : 0.0f;
+  L[3] = t.x1in ? (t.x1lo ? a1 : b1) : 0.0f;
 }
 
 // Bilinear value and (GRAD) its derivatives in x and y inside the cell.

@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import multiprocessing as mp
 import hashlib
 import json
 import os
@@ -322,6 +323,15 @@ def host_info():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
+def _oracle_ransac_job(job):
+    """One pair's oracle RANSAC (a process-pool job; the oracle is imported
+    in the worker)."""
+    from oracle import ransac as oref
+    corr, n_hyp, seed, pair = job
+    oref.ransac_ref(corr, n_hyp, 3.0, seed, pair=pair)
+    return corr.shape[1]
+
+
 def cpu_oracle_extras():
     """The oracle on the other workloads, timed on the host (bounded samples):
     the host's CPU model and core count; ACA and SKS on one core (4096
@@ -356,6 +366,23 @@ def cpu_oracle_extras():
     t = time.perf_counter()
     oref.ransac_ref(cs.corr, 4096, 3.0, 2)
     dt_r = time.perf_counter() - t
+    # all cores: the single-pair workload in every worker process at once, and
+    # every 8th pair of the 512-pair batch spread over the workers
+    workers = max(1, min(16, host_info()["usable_cpus"]))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_ransac_job, [(cs.corr[:, :64], 64, 2, 0)] * workers)   # warm the workers
+        t = time.perf_counter()
+        pool.map(_oracle_ransac_job, [(cs.corr, 4096, 2, 0)] * workers, chunksize=1)
+        dt_r_all = time.perf_counter() - t
+        cb = synth.config3()
+        jobs = [(np.ascontiguousarray(cb.corr[:, cb.off[p]:cb.off[p + 1]]), 1024, 3, p)
+                for p in range(0, 512, 8)]
+        jobs.sort(key=lambda j: -j[0].shape[1])
+        t = time.perf_counter()
+        pool.map(_oracle_ransac_job, jobs, chunksize=1)
+        dt_b = time.perf_counter() - t
+    hp_b = float(sum(j[0].shape[1] for j in jobs)) * 1024
     pb = synth.patches(64, 4)
     t = time.perf_counter()
     ow.loss_and_grad(pb.offsets, pb.img, pb.tgt)
@@ -364,6 +391,15 @@ def cpu_oracle_extras():
             "ransac_2000x4096": {"hyp_pts_per_s": 2000 * 4096 / dt_r, "seconds": dt_r, "cores": 1,
                                  "sample": "oracle RANSAC (Philox + Floyd, float64 ACA, float64 "
                                            "transfer-error test) on the full single-pair workload"},
+            "ransac_2000x4096_all_cores": {
+                "hyp_pts_per_s": workers * 2000 * 4096 / dt_r_all, "seconds": dt_r_all,
+                "cores": workers,
+                "sample": f"the same single-pair oracle run in {workers} processes at once "
+                          f"(aggregate rate)"},
+            "ransac_batched_512x1024": {
+                "hyp_pts_per_s": hp_b / dt_b, "seconds": dt_b, "cores": workers,
+                "sample": f"oracle RANSAC on every 8th pair of the 512-pair batch (64 pairs, "
+                          f"{hp_b:.3g} hyp-pts, 1024 hypotheses each) over {workers} processes"},
             "warp_l1_128x128": {"patches_per_s": 64 / dt_w, "seconds": dt_w,
                                 "cores": torch.get_num_threads(),
                                 "sample": "float64 autograd through the DLT solve, bilinear warp "

@@ -98,7 +98,7 @@ int hg_solve_sk(const double *obj, const float *dst, int64_t n, int64_t ld, floa
 
 /* ---- three-point affine ---------------------------------------------------
  * The affine map through three correspondences M, N, P as H_A2^-1 H_A1
- * (Sec. 4.4, eq. AffineACA, 33 operations up to scale), normalised by its
+ * (Sec. 5.2, eq. AffineACA, 33 operations up to scale), normalised by its
  * third-row entry f_A1 (one division, six multiplications), in double
  * precision on float inputs.
  *   src, dst  6 planes each of n floats at stride ld: x_M y_M x_N y_N x_P y_P.

@@ -1,4 +1,4 @@
-"""Build libhomog.so (HIP, gfx950) next to this file, and the oracle's C parts.
+"""Build libhomog.so (HIP, gfx950) next to this file.
 
 Usage: python -m paper_2402_18008_amd.build   (or build() from Python)
 """

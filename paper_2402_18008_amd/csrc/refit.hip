@@ -13,7 +13,9 @@
 // then forms the 3 x 3 Gram matrix
 //   M^T M = S2u - S1u S0^-1 S1u + S2v - S1v S0^-1 S1v
 // (S0 = X^T X, S1u = X^T D_u X, S2u = X^T D_u^2 X), takes its eigenvector of
-// smallest eigenvalue by cyclic Jacobi rotations, recovers h1, h2,
+// smallest eigenvalue as the dominant eigenvector of its adjugate (repeated
+// squaring; cyclic Jacobi rotations when the two smallest eigenvalues are too
+// close for that to converge), recovers h1, h2,
 // denormalises and writes the power-of-two scaled float H. Points are read
 // twice; the second pass of a pair of RANSAC size hits L2.
 #include <cmath>

@@ -305,7 +305,7 @@ __device__ __forceinline__ uint32_t sk_simplified_solve(const SkPattern &p, cons
   return (p.flags | (quad_side_thin(d) ? kNearDegenerate : 0u));
 }
 
-// Affine map through three correspondences M, N, P (Sec. 4.4, eq. AffineACA):
+// Affine map through three correspondences M, N, P (Sec. 5.2, eq. AffineACA):
 // H_A2^-1 H_A1 (33 operations, third row (0, 0, f_A1)), then its top two rows
 // times 1 / f_A1, giving A = [a11 a12 a13; a21 a22 a23] with x' = A (x, y, 1).
 // s, d: x_M y_M x_N y_N x_P y_P. Returns the near-degeneracy bit (the triangle

@@ -103,25 +103,33 @@ def test_degenerate_and_nonfinite(method):
 
 
 def test_config1_full_size_sampled():
-    """2^26 quadruples in the launch the benchmark times; every planted
-    near-degenerate set is flagged and a 1-in-1024 sample plus all flagged sets
-    match the oracle."""
+    """2^26 quadruples in the launch the benchmark times, by ACA and by SKS;
+    every planted near-degenerate set is flagged, the near-degeneracy bits of
+    the two methods agree, and a 1-in-1024 sample plus every flagged set match
+    the oracle."""
     require_gpu()
     import paper_2402_18008_amd as hgpu
     n = 1 << 26
-    announce("solve4 aca config1 generating 2^26 quadruples")
+    announce("solve4 config1 generating 2^26 quadruples")
     src, dst, lab = synth.config1(n, workers=16)
     S = torch.from_numpy(src).cuda()
     D = torch.from_numpy(dst).cuda()
-    announce("solve4 aca config1 launch")
-    H, f = hgpu.hg_solve4(S, D, "aca")
-    torch.cuda.synchronize()
-    fg = f.cpu().numpy()
-    assert np.all(fg[lab == 1] & 1), "planted degeneracies must be flagged"
-    sel = np.unique(np.concatenate([np.arange(0, n, 1024), np.nonzero(fg)[0][:20000]]))
-    Hs = H[:, torch.from_numpy(sel).cuda()].cpu().numpy().T.reshape(-1, 3, 3)
-    st = check(src[:, sel], dst[:, sel], "aca", Hs, fg[sel], "config1")
-    print("config1", st, "flagged", int((fg != 0).sum()))
+    flags = {}
+    for method in ("aca", "sks"):
+        announce(f"solve4 {method} config1 launch")
+        H, f = hgpu.hg_solve4(S, D, method)
+        torch.cuda.synchronize()
+        fg = f.cpu().numpy()
+        assert np.all(fg[lab == 1] & 1), "planted degeneracies must be flagged"
+        sel = np.unique(np.concatenate([np.arange(0, n, 1024), np.nonzero(fg)[0]]))
+        Hs = H[:, torch.from_numpy(sel).cuda()].cpu().numpy().T.reshape(-1, 3, 3)
+        del H
+        st = check(src[:, sel], dst[:, sel], method, Hs, fg[sel], f"config1 {method}")
+        print("config1", method, st, "flagged", int((fg != 0).sum()), "checked", len(sel))
+        flags[method] = fg
+    # the near-degeneracy bit is the same test on the same areas (the zero-H bit
+    # may differ: SKS divides, ACA does not)
+    assert np.array_equal(flags["aca"] & 1, flags["sks"] & 1)
 
 
 def test_stream_copy():

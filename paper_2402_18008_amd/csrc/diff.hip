@@ -154,37 +154,52 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_buffer(const float *I, i
       const_cast<float *>(I), 0, static_cast<int>(static_cast<uint32_t>(P) * 4u), 0x00020000);
 }
 
+// Position clamped into [-2, w + 1] x [-2, h + 1] first (nan to -2): a cell
+// it moves has all four taps outside before and after, and the cell indices
+// stay small (h, w <= 32768). A row above the image gives a row offset that
+// wraps past 2^31 as an unsigned number and is replaced by kFarOffset; rows
+// at or below h lie at or past the buffer's end: both read 0, and so does a
+// cell with both columns outside (which then reads no memory). Otherwise
+// columns are masked: tap x0 exists iff 0 <= ix < w, x0 + 1 iff
+// -1 <= ix < w - 1.
 __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
-  if (!(fabs(sx) < 1.0e6) || !(fabs(sy) < 1.0e6)) {   // far outside or nan: all taps outside
-    sx = -4.0;
-    sy = -4.0;
-  }
+  sx = fmin(fmax(sx, -2.0), static_cast<double>(w + 1));
+  sy = fmin(fmax(sy, -2.0), static_cast<double>(h + 1));
   const double fx = floor(sx), fy = floor(sy);
   TapAddr t;
   t.ax = static_cast<float>(sx - fx);
   t.ay = static_cast<float>(sy - fy);
   const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
-  // cells with a tap inside the image; any other cell has all four taps outside
-  const bool near = ix >= -1 && ix < w && iy >= -1 && iy < h;
-  const uint32_t row0 = near && iy >= 0 ? static_cast<uint32_t>(iy * w) * 4u : kFarOffset;
-  const uint32_t row1 = near ? static_cast<uint32_t>((iy + 1) * w) * 4u : kFarOffset;
   const int cp = max(min(ix, w - 2), 0);
-  t.o0 = row0 + static_cast<uint32_t>(cp) * 4u;
-  t.o1 = row1 + static_cast<uint32_t>(cp) * 4u;
-  t.x0in = ix >= 0;
-  t.x1in = ix + 1 < w;
+  const int w4 = 4 * w;
+  const uint32_t o = static_cast<uint32_t>(__mul24(iy, w4) + 4 * cp);
+  const bool cols = static_cast<uint32_t>(ix + 1) <= static_cast<uint32_t>(w);   // -1 <= ix < w
+  t.o0 = cols ? min(o, kFarOffset) : kFarOffset;
+  t.o1 = cols ? min(o + static_cast<uint32_t>(w4), kFarOffset) : kFarOffset;
+  t.x0in = static_cast<uint32_t>(ix) < static_cast<uint32_t>(w);
+  t.x1in = static_cast<uint32_t>(ix + 1) < static_cast<uint32_t>(w);
   t.x0hi = ix != cp;
   t.x1lo = ix + 1 == cp;
   return t;
 }
 
-// The four taps of a cell (x0 y0, x1 y0, x0 y1, x1 y1; column-masked, rows
-// outside read 0).
-__device__ __forceinline__ void tap_load(__amdgpu_buffer_rsrc_t r, const TapAddr &t, float L[4]) {
-  const auto p0 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o0, 0, 0);
-  const auto p1 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o1, 0, 0);
-  const float a0 = __uint_as_float(p0[0]), b0 = __uint_as_float(p0[1]);
-  const float a1 = __uint_as_float(p1[0]), b1 = __uint_as_float(p1[1]);
+// The column pairs of a cell's two rows, as loaded (rows outside read 0).
+struct TapRaw {
+  decltype(__builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t(), 0, 0, 0)) p0, p1;
+};
+
+__device__ __forceinline__ TapRaw tap_load(__amdgpu_buffer_rsrc_t r, const TapAddr &t) {
+  TapRaw q;
+  q.p0 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o0, 0, 0);
+  q.p1 = __builtin_amdgcn_raw_buffer_load_b64(r, t.o1, 0, 0);
+  return q;
+}
+
+// The four taps of a cell (x0 y0, x1 y0, x0 y1, x1 y1; column-masked) from
+// its loaded column pairs.
+__device__ __forceinline__ void tap_pick(const TapAddr &t, const TapRaw &q, float L[4]) {
+  const float a0 = __uint_as_float(q.p0[0]), b0 = __uint_as_float(q.p0[1]);
+  const float a1 = __uint_as_float(q.p1[0]), b1 = __uint_as_float(q.p1[1]);
   L[0] = t.x0in ? (t.x0hi ? b0 : a0) : 0.0f;
   L[1] = t.x1in ? (t.x1lo ? a0 : b0) : 0.0f;
   L[2] = t.x0in ? (t.x0hi ? b1 : a1) : 0.0f;
@@ -346,8 +361,9 @@ enum WarpMode {
 // the loss (kLoss, kLossGrad; thread 0), the warped image (kStore), and dL/dH
 // to gHout (kGrad, kGradStored, kLossGrad; thread 0, 9 doubles).
 // The gradient of the loss through q = G p, position (q0, q1) / q2: with
-// g = dL/dI_w at a pixel, (gx, gy) = g grad I there and iq = 1/q2,
-// dL/dG row 1 += gx iq p, row 2 += gy iq p, row 3 += -(gx sx + gy sy) iq p.
+// g = dL/dI_w at a pixel (gl sign(r) for the L1 loss, gl a per-patch
+// constant), (a0, a1) = g iq grad I there and iq = 1/q2,
+// dL/dG row 1 += a0 p, row 2 += a1 p, row 3 += -(a0 sx + a1 sy) p.
 template <int MODE, int NT, bool ALIGNED>
 __device__ __forceinline__ void warp_block(const double *Hb, const float *__restrict__ img,
                                            const float *__restrict__ tgt, float gl, int h, int w,
@@ -391,10 +407,13 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
       sf[k] = 0.0f;
     }
   };
-  int since = 0;
-  for (int i0 = threadIdx.x; i0 < P; i0 += NT * kUnroll) {
+  // one iteration of kUnroll pixels per thread; TAIL: the last, partly past
+  // the patch
+  auto iteration = [&](int i0, auto tail_tag) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
     TapAddr ta[kUnroll];
-    float L[kUnroll][4], tv[kUnroll], sxf[kUnroll], syf[kUnroll], iqf[kUnroll];
+    TapRaw raw[kUnroll];
+    float tv[kUnroll], sxf[kUnroll], syf[kUnroll], iqf[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const double yd = static_cast<double>(pw.y[u]);
@@ -412,59 +431,77 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
       const double iq = recip(q2);
       const double sx = q0 * iq, sy = q1 * iq;
       ta[u] = tap_addr(sx, sy, h, w);
+      if (TAIL && i0 + u * NT >= P) ta[u].o0 = ta[u].o1 = kFarOffset;   // past the patch: 0
       if (GRAD) {
         sxf[u] = static_cast<float>(sx);
         syf[u] = static_cast<float>(sy);
         iqf[u] = static_cast<float>(iq);
       }
-      tap_load(rs, ta[u], L[u]);
+      raw[u] = tap_load(rs, ta[u]);
       if (MODE != kStore)
         tv[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
             rt, static_cast<uint32_t>(i0 + u * NT) * 4u, 0, 0));
     }
+    // every pixel's loads are issued before the first is used
+    __builtin_amdgcn_sched_barrier(0);
+    // TAIL: a pixel past the patch read 0 for its taps and its target
+    // (r = 0) and is masked out of the gradient without a branch, so that no
+    // pixel's loads move into a conditional block
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int i = i0 + u * NT;
-      if (i < P) {
-        const Tap t = tap_eval<GRAD>(ta[u], L[u]);
-        if (MODE == kStore) warped[static_cast<int64_t>(b) * P + i] = t.v;
-        const float r = t.v - tv[u];
-        if (LOSS) sf[9] += fabsf(r);
-        if (GRAD) {
-          float g;
-          if (MODE == kGradStored)
-            g = tv[u];
-          else
-            g = r > 0.0f ? gl : (r < 0.0f ? -gl : 0.0f);
-          const float gx = g * t.dvdx, gy = g * t.dvdy;
-          const float a0 = gx * iqf[u], a1 = gy * iqf[u];
-          const float a2 = -fmaf(gx, sxf[u], gy * syf[u]) * iqf[u];
-          const float yf = static_cast<float>(pw.y[u]);
-          if (ALIGNED) {
-            sf[0] += a0;
-            sf[3] += a1;
-            sf[6] += a2;
-          } else {
-            const float xf = static_cast<float>(pw.x[u]);
-            sf[0] = fmaf(a0, xf, sf[0]);
-            sf[3] = fmaf(a1, xf, sf[3]);
-            sf[6] = fmaf(a2, xf, sf[6]);
-          }
-          sf[1] = fmaf(a0, yf, sf[1]);
-          sf[2] += a0;
-          sf[4] = fmaf(a1, yf, sf[4]);
-          sf[5] += a1;
-          sf[7] = fmaf(a2, yf, sf[7]);
-          sf[8] += a2;
+      const bool in = !TAIL || i < P;
+      float L[4];
+      tap_pick(ta[u], raw[u], L);
+      const Tap t = tap_eval<GRAD>(ta[u], L);
+      if (MODE == kStore && in) warped[static_cast<int64_t>(b) * P + i] = t.v;
+      const float r = t.v - tv[u];
+      if (LOSS) sf[9] += fabsf(r);
+      if (GRAD) {
+        // g iq
+        float gi;
+        if (MODE == kGradStored) {
+          gi = tv[u] * iqf[u];
+        } else {
+          const float gq = gl * iqf[u];
+          gi = r > 0.0f ? gq : (r < 0.0f ? -gq : 0.0f);
         }
+        gi = in ? gi : 0.0f;
+        const float a0 = gi * t.dvdx, a1 = gi * t.dvdy;
+        const float na2 = fmaf(a0, sxf[u], a1 * syf[u]);   // -(row 3 term)
+        const float yf = static_cast<float>(pw.y[u]);
+        if (ALIGNED) {
+          sf[0] += a0;
+          sf[3] += a1;
+          sf[6] -= na2;
+        } else {
+          const float xf = static_cast<float>(pw.x[u]);
+          sf[0] = fmaf(a0, xf, sf[0]);
+          sf[3] = fmaf(a1, xf, sf[3]);
+          sf[6] = fmaf(-na2, xf, sf[6]);
+        }
+        sf[1] = fmaf(a0, yf, sf[1]);
+        sf[2] += a0;
+        sf[4] = fmaf(a1, yf, sf[4]);
+        sf[5] += a1;
+        sf[7] = fmaf(-na2, yf, sf[7]);
+        sf[8] -= na2;
       }
     }
+  };
+  // full iterations (every pixel of the workgroup inside the patch), then at
+  // most one partial one; the fold cadence is per iteration
+  int since = 0;
+  int i0 = threadIdx.x;
+  for (; i0 - static_cast<int>(threadIdx.x) + NT * kUnroll <= P; i0 += NT * kUnroll) {
+    iteration(i0, std::false_type());
     pw.advance();
     if (++since == kFold) {
       fold();
       since = 0;
     }
   }
+  if (i0 - static_cast<int>(threadIdx.x) < P) iteration(i0, std::true_type());
   fold();
   if (LOSS && !GRAD) {
     double s1[1] = {sd[9]}, o1[1];
@@ -483,8 +520,9 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
   }
 }
 
+// Per-pixel kernels: at least 4 waves per SIMD (at most 128 VGPRs).
 template <int MODE, int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void warp_kernel(const double *__restrict__ H,
+__global__ __launch_bounds__(NT, 4) void warp_kernel(const double *__restrict__ H,
                                                   const float *__restrict__ img,
                                                   const float *__restrict__ tgt,
                                                   const float *__restrict__ grad_loss, int h,
@@ -513,7 +551,7 @@ __device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, 
 }
 
 template <int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void photo_fwd_kernel(const float *__restrict__ off,
+__global__ __launch_bounds__(NT, 4) void photo_fwd_kernel(const float *__restrict__ off,
                                                        const float *__restrict__ img,
                                                        const float *__restrict__ tgt, int h,
                                                        int w, RectArgs ra,
@@ -526,7 +564,7 @@ __global__ __launch_bounds__(NT) void photo_fwd_kernel(const float *__restrict__
 // grad_offsets = grad_loss[b] dL_b/d offsets_b; with STEP, instead
 // offsets_b -= step * float(dL_b/d offsets_b) in place (grad_loss = 1).
 template <bool STEP, int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void photo_bwd_kernel(
+__global__ __launch_bounds__(NT, 4) void photo_bwd_kernel(
     float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ grad_loss, int h, int w, RectArgs ra, float step,
     float *__restrict__ goff) {
@@ -554,7 +592,7 @@ __global__ __launch_bounds__(NT) void photo_bwd_kernel(
 // Loss and its gradient in one pass over img and tgt: loss[b] and
 // grad_unit[b] = dloss[b]/d offsets_b (grad_loss = 1).
 template <int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void photo_fwd_grad_kernel(
+__global__ __launch_bounds__(NT, 4) void photo_fwd_grad_kernel(
     const float *__restrict__ off, const float *__restrict__ img, const float *__restrict__ tgt,
     int h, int w, RectArgs ra, float *__restrict__ loss, float *__restrict__ grad_unit) {
   __shared__ double Hs[9];

@@ -48,6 +48,19 @@ def solver_hash():
     return h.hexdigest()[:16]
 
 
+def oracle_fp64_error():
+    """The oracle's own float64 error against the exact rational DLT per
+    workload (max and p99 over 512 problems), as stored beside the tests by a
+    script that calls only the oracle; None if the file is absent."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_fp64_error.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return {k: {"max": v["max"], "p99": v["p99"], "n": v["n"]} for k, v in t.items()}
+
+
 def measured_traffic(n):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current solver source."""
@@ -768,6 +781,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(src, dst, n, workers)
         if args.part == "all":
             extra["cpu_oracle"] = cpu_oracle_extras()
+    if args.part == "all":
+        extra["oracle_fp64_error"] = oracle_fp64_error()
     print(json.dumps(out), flush=True)
 
 

@@ -87,6 +87,26 @@ def h_aca(src, dst):
     return torch.stack([torch.stack(r, dim=-1) for r in H], dim=-2)
 
 
+def h_aca_poly(src, dst):
+    """General ACA through its polynomial form (Sec. 4.5, eq. H_11, with the
+    third-column reading of ``homography.aca_poly_s``) on torch tensors, src,
+    dst (B, 8); H (B, 3, 3) at the same scale as ``h_aca``. Autograd through it
+    differentiates the nine polynomials of the corner coordinates directly."""
+    H = hg.aca_poly_s(list(src.T), list(dst.T))
+    return torch.stack([torch.stack(r, dim=-1) for r in H], dim=-2)
+
+
+def aca_poly_vjp(src, dst, grad_H):
+    """(dH/dsrc)^T grad_H and (dH/ddst)^T grad_H, each (B, 8), for H = h_aca_poly
+    and grad_H (B, 3, 3), by float64 autograd through the polynomial form."""
+    s = torch.as_tensor(src, dtype=torch.float64).clone().requires_grad_(True)
+    d = torch.as_tensor(dst, dtype=torch.float64).clone().requires_grad_(True)
+    g = torch.as_tensor(grad_H, dtype=torch.float64)
+    H = h_aca_poly(s, d)
+    gs, gd = torch.autograd.grad((H * g).sum(), (s, d))
+    return gs, gd
+
+
 def aca_vjp(src, dst, grad_H):
     """(dH/dsrc)^T grad_H and (dH/ddst)^T grad_H, each (B, 8), for H = h_aca
     and grad_H (B, 3, 3), by float64 autograd."""

@@ -46,7 +46,8 @@ def test_rect_forward_backward():
     """The rectangle H is ACA's with the rectangle's source corners: raw
     values within 1e-12 of the oracle's general ACA, equal up to scale to
     Algorithm 1 and to the exact solution; its vector-Jacobian product is the
-    oracle's (float64 autograd through general ACA and through Algorithm 1)."""
+    oracle's (float64 autograd through general ACA, through its polynomial
+    form and through Algorithm 1)."""
     require_gpu()
     import paper_2402_18008_amd as hgpu
     rng = np.random.default_rng(0)
@@ -67,6 +68,10 @@ def test_rect_forward_backward():
                                 retain_graph=True)
     gref = gd.numpy().reshape(-1, 4, 2)[:, [0, 1, 3, 2], :]      # back to TL TR BR BL
     assert rel(g, gref).max() < 1e-6     # float output
+    # d(H)/d(offsets) through ACA's polynomial form (eq. H_11) gives the same products
+    _, gdp = ow.aca_poly_vjp(torch.from_numpy(src), torch.from_numpy(dst),
+                             torch.from_numpy(gH).reshape(-1, 3, 3))
+    assert rel(g, gdp.numpy().reshape(-1, 4, 2)[:, [0, 1, 3, 2], :]).max() < 1e-6
     # the same direction through Algorithm 1: H differs by a per-patch scale
     # s(offsets), so grad_H projected orthogonally to H gives equal products
     Hn = Ha.detach().numpy().reshape(-1, 9)
@@ -227,6 +232,9 @@ def test_general_aca_forward_backward(B):
     g = np.concatenate([gs.cpu().numpy(), gd.cpu().numpy()], axis=1)
     gr = np.concatenate([gsr.numpy(), gdr.numpy()], axis=1)
     assert rel(g, gr).max() < 1e-6
+    # the same products through ACA's polynomial form (eq. H_11)
+    gsp, gdp = ow.aca_poly_vjp(s64, d64, torch.from_numpy(gH).reshape(B, 3, 3))
+    assert rel(g, np.concatenate([gsp.numpy(), gdp.numpy()], axis=1)).max() < 1e-6
     # one side only
     _, gd2 = hgpu.hg_aca_bwd(s, d, torch.from_numpy(gH).cuda(), want_src=False)
     torch.cuda.synchronize()

@@ -124,6 +124,31 @@ def test_general_aca_matches_dlt_and_finite_differences():
         assert ((g - fd).abs() <= 1e-7 * scale).all(), (which, (g - fd).abs().max())
 
 
+def test_polynomial_form_has_the_same_derivative():
+    """The polynomial form (eq. H_11 with the f3 reading) is the same function
+    as the product form at the same scale, so reverse mode through either gives
+    the same vector-Jacobian products; central finite differences of the
+    polynomial form agree too."""
+    src, dst, _ = synth.quadruples(64, 22)
+    s = torch.as_tensor(src.T.astype(np.float64))
+    d = torch.as_tensor(dst.T.astype(np.float64))
+    Hp, Ha = warp.h_aca_poly(s, d), warp.h_aca(s, d)
+    scale = Ha.abs().amax(dim=(1, 2), keepdim=True)
+    assert ((Hp - Ha).abs() <= 1e-12 * scale).all()
+    rng = np.random.default_rng(4)
+    gH = torch.as_tensor(rng.normal(size=(64, 3, 3)))
+    gps, gpd = warp.aca_poly_vjp(s, d, gH)
+    gas, gad = warp.aca_vjp(s, d, gH)
+    for gp, ga in ((gps, gas), (gpd, gad)):
+        sc = ga.abs().max(dim=1, keepdim=True).values
+        assert ((gp - ga).abs() <= 1e-11 * sc).all()
+    for k in range(8):
+        e = torch.zeros_like(d)
+        e[:, k] = 1e-4
+        fd = ((warp.h_aca_poly(s, d + e) - warp.h_aca_poly(s, d - e)) * gH).sum((1, 2)) / 2e-4
+        assert ((gpd[:, k] - fd).abs() <= 1e-7 * gpd.abs().max(dim=1).values).all()
+
+
 def test_refinement_moves_towards_the_true_offsets():
     """Gradient-step refinement on patches whose target is an integer
     translation of the source: six steps from a perturbed start reduce every

@@ -149,6 +149,44 @@ def test_other_patch_sizes():
             compare_oracle(pbl, L, g, slice(None), f"{h}x{w} fused={fused}")
 
 
+@pytest.mark.parametrize("fused", [True, "recompute", False])
+def test_tiny_patches_one_partial_iteration(fused):
+    """Patches smaller than one iteration of the pixel loop (every pixel lies
+    in the masked last iteration) and widths of 2 (one column pair spans the
+    row), against the oracle."""
+    require_gpu()
+    for B, h, w, seed in ((3, 2, 2, 51), (4, 3, 5, 52), (2, 8, 8, 53), (2, 5, 2, 54)):
+        rng = np.random.default_rng(seed)
+        pbl = type("PB", (), {})()
+        pbl.img = rng.normal(size=(B, h, w)).astype(np.float32)
+        pbl.tgt = rng.normal(size=(B, h, w)).astype(np.float32)
+        pbl.offsets = rng.uniform(-0.4, 0.4, (B, 4, 2)).astype(np.float32)
+        announce(f"warp-l1 fwd+bwd {B} patches {h}x{w} fused={fused}")
+        L, g = run_pipeline(pbl, fused=fused)
+        compare_oracle(pbl, L, g, slice(None), f"{h}x{w} fused={fused}")
+
+
+def test_one_pixel_wide_images():
+    """w = 1 (the warp kernels accept it): a tap's column pair then reaches
+    into the next row, and past the buffer's end on the last row. The stored
+    warp equals the oracle's for the identity and for a small shift."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    rng = np.random.default_rng(61)
+    B, h, w = 3, 9, 1
+    img = torch.from_numpy(rng.normal(size=(B, h, w)).astype(np.float32)).cuda()
+    for dy in (0.0, 0.3, -0.7):
+        Hd = torch.eye(3, dtype=torch.float64).repeat(B, 1, 1)
+        Hd[:, 1, 2] = dy
+        announce(f"warp w=1 dy={dy}")
+        Wp = hgpu.hg_warp_store_fwd(Hd.reshape(B, 9).cuda(), img)
+        torch.cuda.synchronize()
+        Wr = ow.warp(img.double().cpu(), Hd)
+        assert (Wr - Wp.double().cpu()).abs().max() < 4e-6, dy
+        if dy == 0.0:
+            assert torch.equal(Wp.cpu(), img.cpu())
+
+
 def test_ragged_sizes_and_stored_form():
     require_gpu()
     import paper_2402_18008_amd as hgpu

@@ -326,6 +326,31 @@ def correspondence_batch(n_pairs, seed, n_min=100, n_max=8000, r_min=0.1, r_max=
     return CorrBatch(corr, off, inl, rs, Hs)
 
 
+def integer_identity_batch(sizes, seed, inlier_ratio=0.4, side=16):
+    """Pairs whose inliers are exact: integer points in [0, side)^2 with
+    x2 = x1 for a fraction inlier_ratio of each pair, and x2 another integer
+    point (x2 != x1) for the rest. Every quantity a sample of four inliers
+    produces is then an integer small enough for exact float arithmetic, so an
+    inlier's transfer error under such a sample's homography is exactly 0.
+    Pair p is drawn from the stream (seed, p + 1); returns a CorrBatch."""
+    ns = np.asarray(sizes, np.int64)
+    off = np.zeros(len(ns) + 1, np.int64)
+    off[1:] = np.cumsum(ns)
+    corr = np.empty((4, int(off[-1])), np.float32)
+    inl = np.empty(int(off[-1]), bool)
+    for p, n in enumerate(ns):
+        rng = np.random.default_rng([seed, p + 1])
+        x1 = rng.integers(0, side, (2, int(n)))
+        is_in = rng.random(int(n)) < inlier_ratio
+        x2 = rng.integers(0, side, (2, int(n)))
+        same = (x2 == x1).all(axis=0) & ~is_in
+        x2[0, same] = (x1[0, same] + 1) % side          # outliers never coincide
+        x2[:, is_in] = x1[:, is_in]
+        corr[:, off[p]:off[p + 1]] = np.concatenate([x1, x2]).astype(np.float32)
+        inl[off[p]:off[p + 1]] = is_in
+    return CorrBatch(corr, off, inl, np.full(len(ns), inlier_ratio), np.tile(np.eye(3), (len(ns), 1, 1)))
+
+
 def _blur_1d(a, axis, sigma, radius):
     k = np.exp(-0.5 * (np.arange(-radius, radius + 1) / sigma) ** 2)
     k /= k.sum()

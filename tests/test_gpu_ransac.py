@@ -253,6 +253,38 @@ def test_config3_persistent_graph_and_autotune():
     g.close()
 
 
+def test_uncertified_and_overflowing_recount_list():
+    """Exact inliers (x2 = x1 on an integer grid) scaled by 2^60: no point
+    lies near the threshold, but for the hypotheses drawn from inliers the
+    float32 certificate's magnitudes reach 1e18, so it certifies nothing and
+    every group of theirs is listed for a float64 recount. A 64-hypothesis
+    item of the batched kernel then lists more groups than the list holds and
+    recounts every hypothesis of the item. Counts, best and masks equal the
+    oracle's: single pair (fused, plain) and batched (two tunings)."""
+    require_gpu()
+    cb = synth.integer_identity_batch([5000, 3000, 700, 8000], 71, inlier_ratio=0.9)
+    cb.corr *= np.float32(2.0 ** 60)
+    from tests.oracle_pool import ransac_refs
+    announce("oracle references of 4 scaled integer pairs")
+    refs = ransac_refs(cb.corr, cb.off, 256, TAU, 5, workers=4)
+    c0 = np.ascontiguousarray(cb.corr[:, cb.off[0]:cb.off[1]])
+    for plain in (False, True):
+        announce(f"ransac scaled integer pair 0 plain={plain}")
+        got = run_single(c0, 256, 5, plain=plain)
+        check_pair(c0, 256, 5, got, label=f"scaled pair 0 plain={plain}", ref=refs[0])
+        assert int(got["best_count"][0]) == int(cb.inlier[cb.off[0]:cb.off[1]].sum())
+    import paper_2402_18008_amd as hgpu
+    br = hgpu.BatchedRansac(torch.from_numpy(cb.corr).cuda(), torch.from_numpy(cb.off).cuda(),
+                            256, TAU, 5, hyp_counts=True)
+    for tune in ((16, 64, 4), (8, 16, 2)):
+        announce(f"batched scaled integer pairs tuning {tune}")
+        br.run(tune)
+        out = np_out(br)
+        for p in range(4):
+            check_pair(cb.corr[:, cb.off[p]:cb.off[p + 1]], 256, 5, pair_view(cb, out, p), pair=p,
+                       label=f"scaled pair {p} tuning {tune}", ref=refs[p])
+
+
 def test_outputs_without_hypothesis_counts():
     """Without the per-hypothesis count output the kernels recount in float64
     only the hypotheses that can still reach the best: best H, count, index

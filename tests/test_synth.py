@@ -167,3 +167,18 @@ def test_patch_offsets_and_shifts():
     assert _uniform_p(pb.offsets.ravel(), -32, 32) > P_MIN
     counts = np.bincount((pb.shift + 16).ravel(), minlength=33)
     assert counts.size == 33 and stats.chisquare(counts).pvalue > P_MIN
+
+
+def test_integer_identity_batch():
+    """Exact-inlier pairs: integer coordinates in range, x2 = x1 exactly on the
+    inliers and never on the outliers, the requested inlier fraction, and the
+    same draw for the same seed."""
+    cb = synth.integer_identity_batch([500, 37, 2000], 5, inlier_ratio=0.7, side=16)
+    assert cb.corr.dtype == np.float32 and cb.off.tolist() == [0, 500, 537, 2537]
+    c = cb.corr.astype(np.float64)
+    assert (c == np.round(c)).all() and c.min() >= 0 and c.max() <= 15
+    same = (c[:2] == c[2:]).all(axis=0)
+    assert np.array_equal(same, cb.inlier)
+    assert abs(cb.inlier.mean() - 0.7) < 0.05
+    again = synth.integer_identity_batch([500, 37, 2000], 5, inlier_ratio=0.7, side=16)
+    assert np.array_equal(again.corr, cb.corr)

@@ -163,6 +163,10 @@ __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *
   return c;
 }
 
+// List length up to which fix_counts recounts every listed group without
+// bounding which hypotheses can still reach the best.
+constexpr uint32_t kBoundMin = 32;
+
 // After the scoring loop (and a workgroup barrier): apply the listed float64
 // recounts to cnt, or on overflow recount every valid hypothesis over all
 // points. With `all` false (per-hypothesis counts are not an output), a
@@ -170,8 +174,9 @@ __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *
 // the hypotheses counted exactly here: its listed points added to its count
 // reach that best (ties included). The others keep a count below their true
 // one, which stays below the best, so the maximum, its lowest index and the
-// mask do not change. ub: LDS scratch of HB words. Ends with a workgroup
-// barrier.
+// mask do not change. The bound costs two barriers and LDS atomics, so with
+// at most kBoundMin entries every listed group is recounted instead. ub: LDS
+// scratch of HB words. Ends with a workgroup barrier.
 __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const double (*H0s)[9],
                            FixList *fx, uint64_t vmask, int nh, uint32_t *cnt, bool all,
                            uint32_t *ub) {
@@ -182,7 +187,8 @@ __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const 
   const uint32_t ne = fx->n;
   if (ne <= kFixCap) {
     uint32_t best = 0u;
-    if (!all && ne > 0u) {
+    const bool bound = !all && ne > kBoundMin;
+    if (bound) {
       // ub[h]: the count so far plus the listed points of h
       for (int h = threadIdx.x; h < nh; h += kThreads) ub[h] = cnt[h];
       __syncthreads();
@@ -201,7 +207,7 @@ __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const 
     for (uint32_t k = wave; k < ne; k += kWaves) {
       const uint32_t c0 = fx->e[k][0], w = fx->e[k][1];
       const uint32_t h = w & 63u, g = (w >> 6) & 7u, wv = (w >> 9) & 3u, rows = (w >> 11) & 31u;
-      if (!all && ub[h] < best) continue;   // cannot reach the best
+      if (bound && ub[h] < best) continue;   // cannot reach the best
       const uint32_t ib = c0 + (g * kGroup * kWaves + wv) * 64u + lane;
       const uint32_t c64 = count_f64(a, X1, Y1, X2, Y2, ib, n, rows, H0s[h]);
       if (lane == 0 && c64) atomicAdd(&cnt[h], c64);

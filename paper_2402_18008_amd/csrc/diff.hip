@@ -491,17 +491,33 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
   };
   // full iterations (every pixel of the workgroup inside the patch), then at
   // most one partial one; the fold cadence is per iteration
-  int since = 0;
+  // The workgroups of one batch are resident together and have equal work,
+  // but the waves' issue arbitration favours some of them, which finish early
+  // and leave their slots idle while the rest run on a thinner CU. Each wave's
+  // priority therefore steps down as it advances (3 in the first quarter of
+  // its iterations, 0 in the last), so that waves behind are issued first.
+  const int n_full = P / (NT * kUnroll);
+  int since = 0, it = 0, prio = 3;
+  __builtin_amdgcn_s_setprio(3);
   int i0 = threadIdx.x;
   for (; i0 - static_cast<int>(threadIdx.x) + NT * kUnroll <= P; i0 += NT * kUnroll) {
+    const int want = 3 - (4 * it) / max(n_full, 1);
+    if (want != prio) {
+      prio = want;
+      if (want == 2) __builtin_amdgcn_s_setprio(2);
+      else if (want == 1) __builtin_amdgcn_s_setprio(1);
+      else __builtin_amdgcn_s_setprio(0);
+    }
     iteration(i0, std::false_type());
     pw.advance();
+    ++it;
     if (++since == kFold) {
       fold();
       since = 0;
     }
   }
   if (i0 - static_cast<int>(threadIdx.x) < P) iteration(i0, std::true_type());
+  __builtin_amdgcn_s_setprio(0);
   fold();
   if (LOSS && !GRAD) {
     double s1[1] = {sd[9]}, o1[1];

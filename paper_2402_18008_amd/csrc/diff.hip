@@ -159,9 +159,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_buffer(const float *I, i
 // stay small (h, w <= 32768). A row above the image gives a row offset that
 // wraps past 2^31 as an unsigned number and is replaced by kFarOffset; rows
 // at or below h lie at or past the buffer's end: both read 0, and so does a
-// cell with both columns outside (which then reads no memory). Otherwise
-// columns are masked: tap x0 exists iff 0 <= ix < w, x0 + 1 iff
-// -1 <= ix < w - 1.
+// cell with both columns outside (its row is taken as -2, so it reads no
+// memory). Otherwise -1 <= ix < w and the columns are masked: tap x0 exists
+// iff ix >= 0, x0 + 1 iff ix <= w - 2; x0 is the pair's second column iff
+// x0 + 1 is outside (w >= 2; with w = 1 the pair starts at column 0), and
+// x0 + 1 its first iff x0 is outside.
 __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
   sx = fmin(fmax(sx, -2.0), static_cast<double>(w + 1));
   sy = fmin(fmax(sy, -2.0), static_cast<double>(h + 1));
@@ -172,14 +174,14 @@ __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) 
   const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
   const int cp = max(min(ix, w - 2), 0);
   const int w4 = 4 * w;
-  const uint32_t o = static_cast<uint32_t>(__mul24(iy, w4) + 4 * cp);
   const bool cols = static_cast<uint32_t>(ix + 1) <= static_cast<uint32_t>(w);   // -1 <= ix < w
-  t.o0 = cols ? min(o, kFarOffset) : kFarOffset;
-  t.o1 = cols ? min(o + static_cast<uint32_t>(w4), kFarOffset) : kFarOffset;
-  t.x0in = static_cast<uint32_t>(ix) < static_cast<uint32_t>(w);
-  t.x1in = static_cast<uint32_t>(ix + 1) < static_cast<uint32_t>(w);
-  t.x0hi = ix != cp;
-  t.x1lo = ix + 1 == cp;
+  const uint32_t o = static_cast<uint32_t>(__mul24(cols ? iy : -2, w4) + 4 * cp);
+  t.o0 = min(o, kFarOffset);
+  t.o1 = min(o + static_cast<uint32_t>(w4), kFarOffset);
+  t.x0in = ix >= 0;
+  t.x1in = ix <= w - 2;
+  t.x0hi = w >= 2 && !t.x1in;
+  t.x1lo = !t.x0in;
   return t;
 }
 

@@ -558,6 +558,8 @@ __global__ __launch_bounds__(NT, 4) void warp_kernel(const double *__restrict__ 
 // ACA with the rectangle's source corners runs in thread 0 of the patch's
 // workgroup into LDS, then the warp; gradients go back through ACA's reverse
 // mode in thread 0. The arithmetic is that of the separate kernels.
+// Only thread 0 reads Hs (load_G and adjugate_backward run in it), so no
+// barrier follows; load_G's barrier then publishes G to the workgroup.
 __device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, double *Hs) {
   if (threadIdx.x == 0) {
     double hh[9];
@@ -565,7 +567,6 @@ __device__ __forceinline__ void rect_to_lds(const float *o, const RectArgs &ra, 
 #pragma unroll
     for (int i = 0; i < 9; ++i) Hs[i] = hh[i];
   }
-  __syncthreads();
 }
 
 template <int NT, bool ALIGNED>

@@ -187,6 +187,23 @@ def test_one_pixel_wide_images():
             assert torch.equal(Wp.cpu(), img.cpu())
 
 
+def test_batch_of_several_rounds():
+    """4096 patches of 64 x 64: about four rounds of resident workgroups (the
+    per-wave priority schedule restarts in each); the single pass, the two
+    passes and the separate stages agree on every patch, and 16 sampled
+    patches match the oracle."""
+    require_gpu()
+    pb = synth.patches(4096, 29, size=64, sigma=3.0, max_shift=8, max_offset=12.0)
+    announce("warp-l1 fwd+bwd 4096 patches 64x64, three forms")
+    L1, g1 = run_pipeline(pb, fused=True)
+    for form in ("recompute", False):
+        L2, g2 = run_pipeline(pb, fused=form)
+        assert np.allclose(L1, L2, rtol=1e-6, atol=0), form
+        assert rel(g1, g2).max() < 1e-5, form
+    idx = np.arange(0, 4096, 256)
+    compare_oracle(pb, L1[idx], g1[idx], idx, "4096 patches, sampled")
+
+
 def test_ragged_sizes_and_stored_form():
     require_gpu()
     import paper_2402_18008_amd as hgpu

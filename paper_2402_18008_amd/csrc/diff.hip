@@ -133,18 +133,21 @@ __device__ __forceinline__ int adjugate_scaled(const double *Hd, double G[9]) {
 // Bilinear sampling with zero padding, split into an address stage and an
 // evaluation stage, so that a thread can issue the loads of several pixels
 // before using any of them. The patch image is read as a raw buffer of its
-// h w floats, whose loads return 0 at byte offsets past its end (the hardware's
-// range check): a row above the image gets an offset past the end, a row below
-// it lies past the end already. Each row of the cell is one 8-byte load of
-// two adjacent columns starting at cp = clamp(x0, 0, w - 2), from which the
-// taps x0 and x0 + 1 are picked, and masked where they lie outside the image.
-// Offsets are 32-bit and never negative.
+// h w floats. The hardware checks a raw buffer load's range per dword: a dword
+// at a byte offset at or past the buffer's end reads 0 without touching
+// memory, also when it is the second half of an 8-byte load whose first half
+// is inside. Each row of the cell is one 8-byte load of two adjacent floats
+// starting at column cp = max(x0, 0) of the row, from which the taps x0 and
+// x0 + 1 are picked and masked where they lie outside the image (at x0 = w - 1
+// the second float is the next row's first, or past the end: masked). A row
+// above the image gets an offset past the end; a row below it lies past the
+// end already. Offsets are 32-bit and never negative.
 constexpr uint32_t kFarOffset = 0x80000000u;   // past every patch (h w <= 2^29 floats)
 
 struct TapAddr {
   uint32_t o0, o1;               // byte offsets of the column pair in rows y0, y0 + 1
-  bool x0in, x1in;               // tap columns inside the image
-  bool x0hi, x1lo;               // tap x0 is the pair's second column / x0 + 1 its first
+  bool x0in, x1in;               // tap columns inside the image (x0 outside: x0 + 1 is
+                                 // the pair's first float)
   float ax, ay;                  // fractional position in the cell
 };
 
@@ -158,12 +161,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_buffer(const float *I, i
 // it moves has all four taps outside before and after, and the cell indices
 // stay small (h, w <= 32768). A row above the image gives a row offset that
 // wraps past 2^31 as an unsigned number and is replaced by kFarOffset; rows
-// at or below h lie at or past the buffer's end: both read 0, and so does a
-// cell with both columns outside (its row is taken as -2, so it reads no
-// memory). Otherwise -1 <= ix < w and the columns are masked: tap x0 exists
-// iff ix >= 0, x0 + 1 iff ix <= w - 2; x0 is the pair's second column iff
-// x0 + 1 is outside (w >= 2; with w = 1 the pair starts at column 0), and
-// x0 + 1 its first iff x0 is outside.
+// at or below h lie at or past the buffer's end: both read 0. A cell with both
+// columns outside (ix < -1 or ix >= w, so 0 <= cp <= w + 1) takes rows -4 and
+// -3, whose offsets 4 (cp - 4 w) and 4 (cp - 3 w) are negative for every
+// w >= 1: it reads no memory. Otherwise -1 <= ix < w and tap x0 exists iff
+// ix >= 0, x0 + 1 iff ix <= w - 2.
 __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) {
   sx = fmin(fmax(sx, -2.0), static_cast<double>(w + 1));
   sy = fmin(fmax(sy, -2.0), static_cast<double>(h + 1));
@@ -172,16 +174,17 @@ __device__ __forceinline__ TapAddr tap_addr(double sx, double sy, int h, int w) 
   t.ax = static_cast<float>(sx - fx);
   t.ay = static_cast<float>(sy - fy);
   const int ix = static_cast<int>(fx), iy = static_cast<int>(fy);
-  const int cp = max(min(ix, w - 2), 0);
+  const int cp = max(ix, 0);
   const int w4 = 4 * w;
   const bool cols = static_cast<uint32_t>(ix + 1) <= static_cast<uint32_t>(w);   // -1 <= ix < w
-  const uint32_t o = static_cast<uint32_t>(__mul24(cols ? iy : -2, w4) + 4 * cp);
+  uint32_t o = static_cast<uint32_t>(__mul24(cols ? iy : -4, w4) + 4 * cp);
+  // the second row's offset is the first's plus one row (kept as one add:
+  // without this the compiler recomputes it from cp with two more operations)
+  asm volatile("" : "+v"(o));
   t.o0 = min(o, kFarOffset);
   t.o1 = min(o + static_cast<uint32_t>(w4), kFarOffset);
   t.x0in = ix >= 0;
   t.x1in = ix <= w - 2;
-  t.x0hi = w >= 2 && !t.x1in;
-  t.x1lo = !t.x0in;
   return t;
 }
 
@@ -198,14 +201,15 @@ __device__ __forceinline__ TapRaw tap_load(__amdgpu_buffer_rsrc_t r, const TapAd
 }
 
 // The four taps of a cell (x0 y0, x1 y0, x0 y1, x1 y1; column-masked) from
-// its loaded column pairs.
+// its loaded column pairs: the pair is (x0, x0 + 1), or (x0 + 1, x0 + 2) when
+// x0 = -1 lies outside.
 __device__ __forceinline__ void tap_pick(const TapAddr &t, const TapRaw &q, float L[4]) {
   const float a0 = __uint_as_float(q.p0[0]), b0 = __uint_as_float(q.p0[1]);
   const float a1 = __uint_as_float(q.p1[0]), b1 = __uint_as_float(q.p1[1]);
-  L[0] = t.x0in ? (t.x0hi ? b0 : a0) : 0.0f;
-  L[1] = t.x1in ? (t.x1lo ? a0 : b0) : 0.0f;
-  L[2] = t.x0in ? (t.x0hi ? b1 : a1) : 0.0f;
-  L[3] = t.x1in ? (t.x1lo ? a1 : b1) : 0.0f;
+  L[0] = t.x0in ? a0 : 0.0f;
+  L[1] = t.x1in ? (t.x0in ? b0 : a0) : 0.0f;
+  L[2] = t.x0in ? a1 : 0.0f;
+  L[3] = t.x1in ? (t.x0in ? b1 : a1) : 0.0f;
 }
 
 // Bilinear value and (GRAD) its derivatives in x and y inside the cell.
@@ -248,9 +252,13 @@ constexpr int kFold = 4;
 // x = threadIdx.x % w, each kUnroll-step k advancing every row by NT kUnroll / w;
 // q = G (x, y, 1) is then a per-thread constant plus y G[:, 1] (3 FMAs).
 // Otherwise (x, y) is walked per pixel and q takes 6 FMAs.
+// ALIGNED keeps each row index as an exact float (rows < 2^24): that is the
+// row of the float gradient sums as it stands, and one conversion gives the
+// double row of q. Otherwise x and y are integers.
 template <int NT, bool ALIGNED>
 struct PixelWalk {
   int x[kUnroll], y[kUnroll];
+  float yf[kUnroll];
   int step_x, step_y, w;
   __device__ __forceinline__ PixelWalk(int w_) : w(w_) {
     constexpr int kStep = NT * kUnroll;
@@ -261,13 +269,22 @@ struct PixelWalk {
       const int i = static_cast<int>(threadIdx.x) + u * NT;
       y[u] = i / w;
       x[u] = i % w;
+      yf[u] = static_cast<float>(y[u]);
     }
+  }
+  __device__ __forceinline__ double row_d(int u) const {
+    return ALIGNED ? static_cast<double>(yf[u]) : static_cast<double>(y[u]);
+  }
+  __device__ __forceinline__ float row_f(int u) const {
+    return ALIGNED ? yf[u] : static_cast<float>(y[u]);
   }
   __device__ __forceinline__ void advance() {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      y[u] += step_y;
-      if (!ALIGNED) {
+      if (ALIGNED) {
+        yf[u] += static_cast<float>(step_y);
+      } else {
+        y[u] += step_y;
         x[u] += step_x;
         if (x[u] >= w) {
           x[u] -= w;
@@ -418,7 +435,7 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
     float tv[kUnroll], sxf[kUnroll], syf[kUnroll], iqf[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const double yd = static_cast<double>(pw.y[u]);
+      const double yd = pw.row_d(u);
       double q0, q1, q2;
       if (ALIGNED) {
         q0 = fma(G[1], yd, A[0]);
@@ -471,7 +488,7 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
         gi = in ? gi : 0.0f;
         const float a0 = gi * t.dvdx, a1 = gi * t.dvdy;
         const float na2 = fmaf(a0, sxf[u], a1 * syf[u]);   // -(row 3 term)
-        const float yf = static_cast<float>(pw.y[u]);
+        const float yf = pw.row_f(u);
         if (ALIGNED) {
           sf[0] += a0;
           sf[3] += a1;

@@ -264,12 +264,25 @@ struct PixelWalk {
     constexpr int kStep = NT * kUnroll;
     step_y = kStep / w;
     step_x = kStep % w;
+    if (ALIGNED) {
+      // one column per thread: pixel threadIdx.x + u NT is NT / w rows below
+      // pixel threadIdx.x + (u - 1) NT
+      const int y0 = static_cast<int>(threadIdx.x) / w;
+      const int x0 = static_cast<int>(threadIdx.x) - y0 * w;
+      const int dy = NT / w;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int i = static_cast<int>(threadIdx.x) + u * NT;
-      y[u] = i / w;
-      x[u] = i % w;
-      yf[u] = static_cast<float>(y[u]);
+      for (int u = 0; u < kUnroll; ++u) {
+        y[u] = y0 + u * dy;
+        x[u] = x0;
+        yf[u] = static_cast<float>(y[u]);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int i = static_cast<int>(threadIdx.x) + u * NT;
+        y[u] = i / w;
+        x[u] = i % w;
+      }
     }
   }
   __device__ __forceinline__ double row_d(int u) const {
@@ -295,27 +308,29 @@ struct PixelWalk {
   }
 };
 
-// Workgroup (NT threads) sum of NV per-thread partials, in double. Result valid in
-// thread 0. Each row of 16 lanes sums its values (row_sum16_f64), then thread k
-// adds the rows' partials of value k in row order: a fixed order, so the result
-// is deterministic.
+// Workgroup (NT threads) sum of NV per-thread partials, in double. Result valid
+// in thread 0. The partials go through LDS: lane (k, r) of the first NV x 16
+// threads adds the partials r, r + 16, r + 32, ... of value k in that order,
+// then the 16 lanes of value k (one DPP row) add their sums in row order. A
+// fixed order, so the result is deterministic; the DPP work is one row scan
+// per value instead of one per value and thread row.
 template <int NV, int NT>
 __device__ __forceinline__ void block_sum(const double (&v)[NV], double (&out)[NV]) {
-  constexpr int kRows = NT / 16;
-  static_assert(NV <= NT, "one thread per value");
-  __shared__ double red[NV][kRows];
+  constexpr int kParts = 16;
+  static_assert(NV * kParts <= NT && NT % kParts == 0, "16 lanes per value");
+  __shared__ double part[NV][NT];
   __shared__ double tot[NV];
   const int t = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const double r = row_sum16_f64(v[k]);
-    if ((t & 15) == 15) red[k][t >> 4] = r;
-  }
+  for (int k = 0; k < NV; ++k) part[k][t] = v[k];
   __syncthreads();
-  if (t < NV) {
-    double x = red[t][0];
-    for (int q = 1; q < kRows; ++q) x += red[t][q];
-    tot[t] = x;
+  if (t < NV * kParts) {
+    const int k = t / kParts, r = t % kParts;
+    double x = part[k][r];
+#pragma unroll
+    for (int j = 1; j < NT / kParts; ++j) x += part[k][j * kParts + r];
+    x = row_sum16_f64(x);
+    if (r == kParts - 1) tot[k] = x;
   }
   __syncthreads();
   if (t == 0) {

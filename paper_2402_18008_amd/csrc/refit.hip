@@ -6,18 +6,20 @@
 //   M = [(I - P) D_u X ; (I - P) D_v X],   X = [x y 1], P = X (X^T X)^-1 X^T,
 // and h1 = (X^T X)^-1 X^T D_u X h3, h2 likewise with D_v.
 //
-// One workgroup per pair: pass 1 sums the selected points' coordinates (the
-// centroids), pass 2 sums 29 moments of the centred coordinates in double
-// (both in batches of 8 points per thread, loads issued ahead of use);
-// the normalisation enters afterwards as powers of the two scales. One lane
-// then forms the 3 x 3 Gram matrix
+// One workgroup per pair, one pass over the points (batches of 8 per thread,
+// loads issued ahead of use): the count and 29 moments of the coordinates
+// taken relative to the pair's first point, summed in double. One lane shifts
+// them to the centroids (binomial expansion: every moment needed for the shift
+// is among the 30 sums), the normalisation enters as powers of the two
+// scales, and the same lane forms the 3 x 3 Gram matrix
 //   M^T M = S2u - S1u S0^-1 S1u + S2v - S1v S0^-1 S1v
 // (S0 = X^T X, S1u = X^T D_u X, S2u = X^T D_u^2 X), takes its eigenvector of
 // smallest eigenvalue as the dominant eigenvector of its adjugate (repeated
 // squaring; cyclic Jacobi rotations when the two smallest eigenvalues are too
 // close for that to converge), recovers h1, h2,
-// denormalises and writes the power-of-two scaled float H. Points are read
-// twice; the second pass of a pair of RANSAC size hits L2.
+// denormalises and writes the power-of-two scaled float H. Moments about a
+// point of the pair rather than the origin keep the shift's cancellation to
+// the ratio of the pair's extent to its spread.
 #include <cmath>
 
 #include "common.hpp"
@@ -27,7 +29,8 @@
 namespace hg {
 
 constexpr int kRefitThreads = 256;
-constexpr int kMoments = 29;   // S0: 5 (n counted in pass 1), S1u, S2u, S1v, S2v: 6 each
+constexpr int kMoments = 29;   // centred: S0 5 (and the count), S1u, S2u, S1v, S2v 6 each
+constexpr int kRaw = 30;       // about the first point: 6 monomials each times 1, u, u^2, v, v^2
 
 // Points are visited kBatch at a time per thread (i0 + j * kRefitThreads),
 // all their loads issued before any is used: one memory round trip per batch
@@ -251,8 +254,49 @@ __host__ __device__ inline void smallest_eigvec3_adj(const double C[3][3], doubl
   for (int i = 0; i < 3; ++i) v[i] = x[i] * r;
 }
 
-// The per-pair solve from the centred moments m (layout of refit_kernel's
-// pass 2), the count n and the centroids: H (row-major, double) = T2^-1 Hn T1,
+// Sums of the monomials {xx, xy, x, yy, y, 1} of x - a, y - b from those of
+// x, y (same weights).
+__host__ __device__ __forceinline__ void shift6(const double *r, double a, double b, double *c) {
+  c[0] = r[0] - 2.0 * a * r[2] + a * a * r[5];
+  c[1] = r[1] - b * r[2] - a * r[4] + a * b * r[5];
+  c[2] = r[2] - a * r[5];
+  c[3] = r[3] - 2.0 * b * r[4] + b * b * r[5];
+  c[4] = r[4] - b * r[5];
+  c[5] = r[5];
+}
+
+// Centred moments m (layout of refit_solve) and the centroids' offsets from the
+// reference point, from the sums r about it: r[0..5] the monomials of (x, y),
+// r[6..11] u times them, r[12..17] u^2 times them, r[18..23] and r[24..29] the
+// same for v; r[5] is the count (> 0). With u = u' - c:
+// sum u M = sum u' M - c sum M and sum u^2 M = sum u'^2 M - 2 c sum u' M + c^2 sum M.
+__host__ __device__ inline void center_moments(const double *r, double *m, double &a, double &b,
+                                               double &c, double &d) {
+  const double n = r[5];
+  a = r[2] / n;
+  b = r[4] / n;
+  c = r[11] / n;
+  d = r[23] / n;
+  double m0[6], mu1[6], mu2[6], mv1[6], mv2[6];
+  shift6(r, a, b, m0);
+  shift6(r + 6, a, b, mu1);
+  shift6(r + 12, a, b, mu2);
+  shift6(r + 18, a, b, mv1);
+  shift6(r + 24, a, b, mv2);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) m[k] = m0[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    m[5 + k] = mu1[k] - c * m0[k];
+    m[11 + k] = mu2[k] - 2.0 * c * mu1[k] + c * c * m0[k];
+    m[17 + k] = mv1[k] - d * m0[k];
+    m[23 + k] = mv2[k] - 2.0 * d * mv1[k] + d * d * m0[k];
+  }
+}
+
+// The per-pair solve from the centred moments m (layout: S0's {xx, xy, x, yy,
+// y}, then u, u^2, v, v^2 times {xx, xy, x, yy, y, 1}), the count n and the
+// centroids: H (row-major, double) = T2^-1 Hn T1,
 // or zeros when X^T X is singular.
 __host__ __device__ inline void refit_solve(const double *m, double n, double cx, double cy,
                                             double cu, double cv, double *h) {
@@ -316,70 +360,57 @@ __global__ __launch_bounds__(kRefitThreads) void refit_kernel(
   const int64_t a = min(max(off[p], int64_t(0)), ld);
   const int64_t b = min(max(off[p + 1], a), ld);
   const float *X1 = corr, *Y1 = corr + ld, *X2 = corr + 2 * ld, *Y2 = corr + 3 * ld;
-  __shared__ double cen[5];
-  // pass 1: count and centroids
-  double s1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // reference point: the pair's first point, selected or not (any point of
+  // the pair keeps the shift's cancellation small); a coordinate that is not
+  // finite there is replaced by 0, so that unselected points never enter the sums
+  double rx = 0.0, ry = 0.0, ru = 0.0, rv = 0.0;
+  if (b > a) {
+    rx = static_cast<double>(X1[a]);
+    ry = static_cast<double>(Y1[a]);
+    ru = static_cast<double>(X2[a]);
+    rv = static_cast<double>(Y2[a]);
+    rx = isfinite(rx) ? rx : 0.0;
+    ry = isfinite(ry) ? ry : 0.0;
+    ru = isfinite(ru) ? ru : 0.0;
+    rv = isfinite(rv) ? rv : 0.0;
+  }
+  double r[kRaw];
+#pragma unroll
+  for (int k = 0; k < kRaw; ++k) r[k] = 0.0;
   for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
     PointBatch pb;
     load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       if (!pb.sel[j]) continue;
-      s1[0] += 1.0;
-      s1[1] += static_cast<double>(pb.x1[j]);
-      s1[2] += static_cast<double>(pb.y1[j]);
-      s1[3] += static_cast<double>(pb.x2[j]);
-      s1[4] += static_cast<double>(pb.y2[j]);
-    }
-  }
-  refit_block_sum(s1);
-  if (threadIdx.x == 0) {
-    const double n = s1[0];
-#pragma unroll
-    for (int k = 1; k < 5; ++k) s1[k] = n > 0.0 ? s1[k] / n : 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) cen[k] = s1[k];
-  }
-  __syncthreads();
-  const double n = cen[0];
-  const int used = static_cast<int>(n);
-  if (used < 4) {   // uniform across the workgroup
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Hout[9 * p + k] = 0.0f;
-      if (n_used) n_used[p] = used;
-      if (flags) flags[p] = static_cast<uint8_t>(kZeroH);
-    }
-    return;
-  }
-  const double cx = cen[1], cy = cen[2], cu = cen[3], cv = cen[4];
-  // pass 2: moments of the centred coordinates; monomials {xx, xy, x, yy, y, 1}
-  double m[kMoments];
-#pragma unroll
-  for (int k = 0; k < kMoments; ++k) m[k] = 0.0;
-  for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
-    PointBatch pb;
-    load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      if (!pb.sel[j]) continue;
-      const double x = static_cast<double>(pb.x1[j]) - cx, y = static_cast<double>(pb.y1[j]) - cy;
-      const double u = static_cast<double>(pb.x2[j]) - cu, v = static_cast<double>(pb.y2[j]) - cv;
+      const double x = static_cast<double>(pb.x1[j]) - rx, y = static_cast<double>(pb.y1[j]) - ry;
+      const double u = static_cast<double>(pb.x2[j]) - ru, v = static_cast<double>(pb.y2[j]) - rv;
       const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
       const double uu = u * u, vv = v * v;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) m[k] += mono[k];
-#pragma unroll
       for (int k = 0; k < 6; ++k) {
-        m[5 + k] += u * mono[k];
-        m[11 + k] += uu * mono[k];
-        m[17 + k] += v * mono[k];
-        m[23 + k] += vv * mono[k];
+        r[k] += mono[k];
+        r[6 + k] += u * mono[k];
+        r[12 + k] += uu * mono[k];
+        r[18 + k] += v * mono[k];
+        r[24 + k] += vv * mono[k];
       }
     }
   }
-  refit_block_sum(m);
+  refit_block_sum(r);
   if (threadIdx.x != 0) return;
+  const double n = r[5];
+  const int used = static_cast<int>(n);
+  if (used < 4) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Hout[9 * p + k] = 0.0f;
+    if (n_used) n_used[p] = used;
+    if (flags) flags[p] = static_cast<uint8_t>(kZeroH);
+    return;
+  }
+  double m[kMoments], da, db, dc, dd;
+  center_moments(r, m, da, db, dc, dd);
+  const double cx = rx + da, cy = ry + db, cu = ru + dc, cv = rv + dd;
   double h[9];
   refit_solve(m, n, cx, cy, cu, cv, h);
   float hf[9];

@@ -415,7 +415,8 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
   const float *T2 = MODE == kStore ? img : tgt;
   const __amdgpu_buffer_rsrc_t rt = patch_buffer(T2 + static_cast<int64_t>(b) * P, P);
   // float partial sums (folded every kFold iterations) and their double totals:
-  // 0..8 the dL/dG terms (ALIGNED: the x-multiplied ones without x), 9 the loss
+  // 0..8 the dL/dG terms, 9 the loss. ALIGNED: x is the thread's column, so the
+  // x-multiplied sums 0, 3, 6 are x times the sums 2, 5, 8, taken at the fold
   constexpr int NS = 10;
   float sf[NS];
   double sd[NS];
@@ -434,10 +435,15 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
     for (int r = 0; r < 3; ++r) A[r] = fma(G[3 * r], xd, G[3 * r + 2]);
   }
   auto fold = [&]() {
+    if (ALIGNED) {
+#pragma unroll
+      for (int k = 0; k < 9; k += 3)
+        sd[k] += static_cast<double>(sf[k + 2]) * static_cast<double>(xcol);
+    }
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const double v = static_cast<double>(sf[k]);
-      sd[k] += (ALIGNED && (k == 0 || k == 3 || k == 6)) ? v * static_cast<double>(xcol) : v;
+      if (ALIGNED && (k == 0 || k == 3 || k == 6)) continue;
+      sd[k] += static_cast<double>(sf[k]);
       sf[k] = 0.0f;
     }
   };
@@ -497,18 +503,15 @@ __device__ __forceinline__ void warp_block(const double *Hb, const float *__rest
         if (MODE == kGradStored) {
           gi = tv[u] * iqf[u];
         } else {
+          // gl iq sign(r), with sign(0) = 0 (and 0 for a nan residual)
           const float gq = gl * iqf[u];
-          gi = r > 0.0f ? gq : (r < 0.0f ? -gq : 0.0f);
+          gi = fabsf(r) > 0.0f ? copysignf(gq, r) : 0.0f;
         }
         gi = in ? gi : 0.0f;
         const float a0 = gi * t.dvdx, a1 = gi * t.dvdy;
         const float na2 = fmaf(a0, sxf[u], a1 * syf[u]);   // -(row 3 term)
         const float yf = pw.row_f(u);
-        if (ALIGNED) {
-          sf[0] += a0;
-          sf[3] += a1;
-          sf[6] -= na2;
-        } else {
+        if (!ALIGNED) {
           const float xf = static_cast<float>(pw.x[u]);
           sf[0] = fmaf(a0, xf, sf[0]);
           sf[3] = fmaf(a1, xf, sf[3]);

@@ -38,6 +38,9 @@ namespace hg {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+// Waves per workgroup of the fused single-pair kernel: 8 (512 threads, two
+// workgroups and four waves per SIMD at about two workgroups per CU).
+constexpr int kFusedWaves = 8;
 
 struct RansacArgs {
   const float *corr;
@@ -127,19 +130,21 @@ constexpr int kGroup = 4;
 // Groups to recount, listed in LDS by the scoring loop (which leaves their
 // points out of its counts) and counted after it, when the loop's point
 // registers are free. Entry: the chunk's first point and (hypothesis |
-// group << 6 | wave << 9 | rows << 11). n counts every append; past kFixCap
+// group << 6 | wave << 9 | rows << 12). n counts every append; past kFixCap
 // the list has overflowed and every hypothesis is recounted in float64.
 constexpr uint32_t kFixCap = 512;
+static_assert(kWaves <= 8 && kFusedWaves <= 8, "a recount entry holds the wave index in 3 bits");
 struct FixList {
   uint32_t n;
   uint32_t e[kFixCap][2];
 };
 
 // Inliers of H (the float H, given as doubles) among `rows` (<= kGroup) rows
-// of 64 points, kWaves * 64 points apart from point ib of this lane (points
+// of 64 points, NW * 64 points apart from point ib of this lane (points
 // at or past n excluded), by the float64 test on the operands read from
 // memory (every row's loads issued before the first test; 32-bit byte
 // offsets from the plane bases, which the pair range keeps below 2^33).
+template <int NW>
 __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *X1,
                                               const float *Y1, const float *X2, const float *Y2,
                                               uint32_t ib, uint32_t n, uint32_t rows,
@@ -147,7 +152,7 @@ __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *
   float x1[kGroup], y1[kGroup], x2[kGroup], y2[kGroup];
 #pragma unroll
   for (int q = 0; q < kGroup; ++q) {
-    const uint32_t j = min(ib + q * kWaves * 64u, n - 1u);   // loads stay inside the pair
+    const uint32_t j = min(ib + q * NW * 64u, n - 1u);   // loads stay inside the pair
     x1[q] = X1[j];
     y1[q] = Y1[j];
     x2[q] = X2[j];
@@ -156,7 +161,7 @@ __device__ __forceinline__ uint32_t count_f64(const RansacArgs &a, const float *
   uint32_t c = 0u;
 #pragma unroll
   for (int q = 0; q < kGroup; ++q) {
-    const uint32_t i = ib + q * kWaves * 64u;
+    const uint32_t i = ib + q * NW * 64u;
     const bool in = inlier_f64(g, x1[q], y1[q], x2[q], y2[q], a.tau);
     c += __popcll(__ballot(in && i < n && static_cast<uint32_t>(q) < rows));
   }
@@ -176,7 +181,8 @@ constexpr uint32_t kBoundMin = 32;
 // one, which stays below the best, so the maximum, its lowest index and the
 // mask do not change. The bound costs two barriers and LDS atomics, so with
 // at most kBoundMin entries every listed group is recounted instead. ub: LDS
-// scratch of HB words. Ends with a workgroup barrier.
+// scratch of HB words. NW: waves per workgroup. Ends with a workgroup barrier.
+template <int NW>
 __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const double (*H0s)[9],
                            FixList *fx, uint64_t vmask, int nh, uint32_t *cnt, bool all,
                            uint32_t *ub) {
@@ -190,11 +196,11 @@ __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const 
     const bool bound = !all && ne > kBoundMin;
     if (bound) {
       // ub[h]: the count so far plus the listed points of h
-      for (int h = threadIdx.x; h < nh; h += kThreads) ub[h] = cnt[h];
+      for (int h = threadIdx.x; h < nh; h += NW * 64) ub[h] = cnt[h];
       __syncthreads();
-      for (uint32_t k = threadIdx.x; k < ne; k += kThreads) {
+      for (uint32_t k = threadIdx.x; k < ne; k += NW * 64) {
         const uint32_t w = fx->e[k][1];
-        atomicAdd(&ub[w & 63u], ((w >> 11) & 31u) * 64u);
+        atomicAdd(&ub[w & 63u], ((w >> 12) & 31u) * 64u);
       }
       __syncthreads();
       // the best exact count: valid hypotheses with nothing listed
@@ -204,21 +210,21 @@ __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const 
       for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, o)));
       best = v;
     }
-    for (uint32_t k = wave; k < ne; k += kWaves) {
+    for (uint32_t k = wave; k < ne; k += NW) {
       const uint32_t c0 = fx->e[k][0], w = fx->e[k][1];
-      const uint32_t h = w & 63u, g = (w >> 6) & 7u, wv = (w >> 9) & 3u, rows = (w >> 11) & 31u;
+      const uint32_t h = w & 63u, g = (w >> 6) & 7u, wv = (w >> 9) & 7u, rows = (w >> 12) & 31u;
       if (bound && ub[h] < best) continue;   // cannot reach the best
-      const uint32_t ib = c0 + (g * kGroup * kWaves + wv) * 64u + lane;
-      const uint32_t c64 = count_f64(a, X1, Y1, X2, Y2, ib, n, rows, H0s[h]);
+      const uint32_t ib = c0 + (g * kGroup * NW + wv) * 64u + lane;
+      const uint32_t c64 = count_f64<NW>(a, X1, Y1, X2, Y2, ib, n, rows, H0s[h]);
       if (lane == 0 && c64) atomicAdd(&cnt[h], c64);
     }
   } else {
-    for (int h = wave; h < nh; h += kWaves) {
+    for (int h = wave; h < nh; h += NW) {
       if (!((vmask >> h) & 1ull)) continue;
       uint32_t c = 0u;
-      for (uint32_t c0 = 0; c0 < n; c0 += kWaves * 64u * kGroup)
-        for (int wv = 0; wv < kWaves; ++wv)
-          c += count_f64(a, X1, Y1, X2, Y2, c0 + wv * 64u + lane, n, kGroup, H0s[h]);
+      for (uint32_t c0 = 0; c0 < n; c0 += NW * 64u * kGroup)
+        for (int wv = 0; wv < NW; ++wv)
+          c += count_f64<NW>(a, X1, Y1, X2, Y2, c0 + wv * 64u + lane, n, kGroup, H0s[h]);
       if (lane == 0) cnt[h] = c;
     }
   }
@@ -243,7 +249,7 @@ __device__ void fix_counts(const RansacArgs &a, int64_t base, uint32_t n, const 
 // hypotheses) and gives up a round that is no longer needed (returns false).
 // Rounds at or past the hint are never needed, so an abandoned round changes
 // no result.
-template <int P, bool TAIL>
+template <int P, bool TAIL, int NW>
 __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1, const float *Y1,
                                             const float *X2, const float *Y2, uint32_t c0,
                                             uint32_t n, const float (*Hs)[9],
@@ -256,7 +262,7 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
   float m1 = 0.0f, m2 = 0.0f, m3 = 0.0f, m4 = 0.0f;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    const uint32_t i = c0 + (p * kWaves + wave) * 64 + lane;
+    const uint32_t i = c0 + (p * NW + wave) * 64 + lane;
     const uint32_t j = (TAIL && i >= n) ? n - 1u : i;   // every load stays inside the pair
     x1[p] = X1[j];
     y1[p] = Y1[j];
@@ -319,7 +325,7 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
             const uint32_t rows = min(kGroup, P - g * kGroup);
             fx->e[k][0] = c0;
             fx->e[k][1] = static_cast<uint32_t>(h) | (static_cast<uint32_t>(g) << 6) |
-                          (static_cast<uint32_t>(wave) << 9) | (rows << 11);
+                          (static_cast<uint32_t>(wave) << 9) | (rows << 12);
           }
         }
       } else {
@@ -333,9 +339,10 @@ __device__ __forceinline__ bool score_chunk(const RansacArgs &a, const float *X1
 
 // Full chunks of P points per lane, then (P = 16) chunks of 8, then one
 // masked tail chunk of just enough 64-point rows per wave (1 to 8), so that a
-// pair's last chunk leaves fewer than 4 x 64 lane slots idle. Counts are
-// integer sums over the points, so the result does not depend on the chunking.
-template <int P>
+// pair's last chunk leaves fewer than NW x 64 lane slots idle (NW: waves per
+// workgroup). Counts are integer sums over the points, so the result does not
+// depend on the chunking.
+template <int P, int NW = kWaves>
 __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, uint32_t n,
                                            const float (*Hs)[9], uint64_t vmask, int nh,
                                            uint32_t *cnt, FixList *fx,
@@ -343,22 +350,24 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
                                            uint32_t hb = 0u) {
   const float *X1 = a.corr + base, *Y1 = a.corr + a.ld + base;
   const float *X2 = a.corr + 2 * a.ld + base, *Y2 = a.corr + 3 * a.ld + base;
-  constexpr uint32_t kChunk = kWaves * 64 * P;
-  constexpr uint32_t kChunk8 = kWaves * 64 * 8;
+  constexpr uint32_t kChunk = NW * 64 * P;
+  constexpr uint32_t kChunk8 = NW * 64 * 8;
   uint32_t c0 = 0;
   for (; c0 + kChunk <= n; c0 += kChunk)
-    if (!score_chunk<P, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb)) return;
+    if (!score_chunk<P, false, NW>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb))
+      return;
   if (P > 8) {
     for (; c0 + kChunk8 <= n; c0 += kChunk8)
-      if (!score_chunk<8, false>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb)) return;
+      if (!score_chunk<8, false, NW>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb))
+        return;
   }
   if (c0 < n) {
     // fewer than kChunk8 points remain: 1 .. 8 rows of 64 points per wave
     const uint32_t rows = (n - c0 + 63u) / 64u;
-    switch ((rows + kWaves - 1) / kWaves) {
+    switch ((rows + NW - 1) / NW) {
 #define HG_TAIL(R) \
   case R:          \
-    score_chunk<R, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb); \
+    score_chunk<R, true, NW>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb); \
     break;
       HG_TAIL(1)
       HG_TAIL(2)
@@ -368,7 +377,7 @@ __device__ __forceinline__ void score_hyps(const RansacArgs &a, int64_t base, ui
       HG_TAIL(6)
       HG_TAIL(7)
       default:
-        score_chunk<8, true>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb);
+        score_chunk<8, true, NW>(a, X1, Y1, X2, Y2, c0, n, Hs, vmask, nh, cnt, fx, stop, hb);
 #undef HG_TAIL
     }
   }
@@ -451,8 +460,8 @@ struct Smem {
   uint32_t skip;
 };
 
-// Process one work item: pair rank r, hypothesis block hb.
-template <int P, int HB>
+// Process one work item: pair rank r, hypothesis block hb (NW waves).
+template <int P, int HB, int NW>
 __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   // pair-major items (all blocks of the largest pair first), or round-major
   // under adaptive termination (round r of every pair before round r + 1)
@@ -506,10 +515,10 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   // 2. score (validity as a wave-uniform bit mask)
   const int lane = threadIdx.x & 63;
   const uint64_t vmask = __ballot(lane < nh && sm.valid[lane] != 0u);
-  score_hyps<P>(a, base, n, sm.H, vmask, nh, sm.cnt, &sm.fix,
+  score_hyps<P, NW>(a, base, n, sm.H, vmask, nh, sm.cnt, &sm.fix,
                 adaptive ? &a.pst[p].stop : nullptr, static_cast<uint32_t>(hb));
   __syncthreads();
-  fix_counts(a, base, n, sm.H0, &sm.fix, vmask, nh, sm.cnt, a.hyp_counts != nullptr, sm.ub);
+  fix_counts<NW>(a, base, n, sm.H0, &sm.fix, vmask, nh, sm.cnt, a.hyp_counts != nullptr, sm.ub);
   if (adaptive) {
     // a wave may have given the round up: then it is at or past the stopping
     // round (which only decreases), and nothing of it is published
@@ -552,11 +561,14 @@ __device__ void run_item(const RansacArgs &a, int64_t item, Smem<HB> &sm) {
   __syncthreads();
 }
 
+// Persistent: kThreads threads, at least 5 workgroups per CU. Single pair
+// (one work item per workgroup): kFusedWaves waves, at least 2 per CU.
 template <int P, int HB, bool PERSISTENT>
-__global__ __launch_bounds__(kThreads, 5) void ransac_kernel(RansacArgs a) {
+__global__ __launch_bounds__(PERSISTENT ? kThreads : kFusedWaves * 64, PERSISTENT ? 5 : 2)
+void ransac_kernel(RansacArgs a) {
   __shared__ Smem<HB> sm;
   if (!PERSISTENT) {
-    run_item<P, HB>(a, blockIdx.x, sm);
+    run_item<P, HB, kFusedWaves>(a, blockIdx.x, sm);
     return;
   }
   for (;;) {
@@ -565,7 +577,7 @@ __global__ __launch_bounds__(kThreads, 5) void ransac_kernel(RansacArgs a) {
     const int64_t item = sm.item;
     __syncthreads();
     if (item >= a.n_items) break;
-    run_item<P, HB>(a, item, sm);
+    run_item<P, HB, kWaves>(a, item, sm);
   }
 }
 
@@ -865,7 +877,7 @@ __global__ __launch_bounds__(kThreads) void plain_score_kernel(RansacArgs a, con
   const uint64_t vmask = __ballot(lane < nh && vs[lane] != 0u);
   score_hyps<P>(a, 0, static_cast<uint32_t>(a.n_single), Hs, vmask, nh, cnt, &fix);
   __syncthreads();
-  fix_counts(a, 0, static_cast<uint32_t>(a.n_single), H0s, &fix, vmask, nh, cnt,
+  fix_counts<kWaves>(a, 0, static_cast<uint32_t>(a.n_single), H0s, &fix, vmask, nh, cnt,
              a.hyp_counts != nullptr, ub);
   if (threadIdx.x < nh)
     counts[h0 + threadIdx.x] = vs[threadIdx.x] ? static_cast<int32_t>(cnt[threadIdx.x]) : -1;
@@ -1168,7 +1180,7 @@ static int launch_fused(const float *corr, int32_t n_pts, int64_t ld, int32_t n_
   a.hbuf = reinterpret_cast<float *>(w);
   a.blockbest = reinterpret_cast<unsigned long long *>(w + align256(36ull * n_hyp));
   KernelFn k = pick_kernel<false>(P, HB);
-  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(a.n_items)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(a.n_items)), dim3(kFusedWaves * 64), 0, s, a);
   if (int st = launched("ransac_kernel<fused>")) return st;
   const int mb = std::max(1, std::min(1024, (n_pts + kThreads - 1) / kThreads));
   hipLaunchKernelGGL(ransac_mask_kernel, dim3(mb), dim3(kThreads), 0, s, a);

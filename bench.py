@@ -422,7 +422,9 @@ def cpu_oracle_extras():
 FP32_FLOP_PER_HYP_PT = 21   # the division-free test as 21 FLOP (FMA = 2): 3 rows x 2 FMA,
                             # 2 FMA residuals, mul + FMA norm, (tau w)^2; the kernel folds
                             # tau into the operands and issues 12 VALU instructions
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3     # the published FP32 vector peak, for packed (two-wide) FP32
+                             # instructions, which these kernels do not issue
+FP32_UNPACKED_TFLOPS = 78.6  # one FP32 FMA per lane and cycle: 256 CUs x 64 lanes x 2 x 2.4 GHz
 
 
 def bench_ransac_single(stream):
@@ -540,6 +542,7 @@ def bench_ransac_batched(stream):
         "speedup_vs_plain": ms_plain / ms_graph,
         "fp32_tflops": FP32_FLOP_PER_HYP_PT * rate / 1e12,
         "fp32_frac_of_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_PEAK_TFLOPS,
+        "fp32_frac_of_unpacked_peak": FP32_FLOP_PER_HYP_PT * rate / 1e12 / FP32_UNPACKED_TFLOPS,
         "adaptive_ms": ms_adaptive, "adaptive_mean_hyps_evaluated": float(n_eval.mean()),
         "adaptive_hyp_pts": float((np.diff(cb.off) * n_eval).sum()),
         "refit_ho_ms": ms_refit, "refit_points": int(total),

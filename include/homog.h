@@ -288,8 +288,8 @@ void hg_graph_destroy(hg_graph *g);
  *   precision inside.
  * hg_aca_rect_bwd: grad_offsets (B x 8 floats) = (dH/d offsets)^T grad_H,
  *   grad_H B x 9 doubles (ACA's reverse mode in the target points).
- * Errors: B < 0, w or r not finite and > 0, non-finite x0/y0, NULL pointer
- * with B > 0 -> HG_EINVAL; B == 0 is a no-op.                                */
+ * Errors: B outside [0, 2^27], w or r not finite and > 0, non-finite x0/y0,
+ * NULL pointer with B > 0 -> HG_EINVAL; B == 0 is a no-op.                   */
 int hg_aca_rect_fwd(const float *offsets, int32_t B, float x0, float y0, float w, float r,
                     double *H, void *stream);
 int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32_t B, float x0, float y0,
@@ -303,8 +303,8 @@ int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32_t B, float
  * hg_aca_bwd: grad_src, grad_dst (B x 8 floats each, either may be NULL) =
  *   (dH/dsrc)^T grad_H and (dH/ddst)^T grad_H, grad_H B x 9 doubles; the
  *   forward quantities are recomputed (nothing is stored between the calls).
- * Errors: B < 0, a NULL input, both outputs NULL -> HG_EINVAL; B == 0 is a
- * no-op.                                                                    */
+ * Errors: B outside [0, 2^30], a NULL input, both outputs NULL -> HG_EINVAL;
+ * B == 0 is a no-op.                                                        */
 int hg_aca_fwd(const float *src, const float *dst, int32_t B, double *H, void *stream);
 int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t B,
                float *grad_src, float *grad_dst, void *stream);
@@ -319,8 +319,8 @@ int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t
  * hg_warp_l1_bwd recomputes everything from H (nothing per pixel is stored)
  * and writes grad_H (B x 9 doubles) = grad_loss[b] * dloss[b]/dH_b, with
  * d|r|/dr = sign(r) (0 at 0) and the floor treated as constant.
- * Errors: B < 0, h or w outside [1, 32768], h w > 2^29, NULL pointer with B > 0 ->
- * HG_EINVAL; B == 0 is a no-op.                                             */
+ * Errors: B outside [0, 2^27], h or w outside [1, 32768], h w > 2^29, NULL
+ * pointer with B > 0 -> HG_EINVAL; B == 0 is a no-op.                                             */
 int hg_warp_l1_fwd(const double *H, const float *img, const float *tgt, int32_t B, int32_t h,
                    int32_t w, float *loss, void *stream);
 int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const float *grad_loss,
@@ -340,8 +340,8 @@ int hg_warp_l1_bwd(const double *H, const float *img, const float *tgt, const fl
  *     in grad_loss, so a later backward only scales grad_unit:
  *     hg_scale_grad(grad_unit, grad_loss, B, grad_offsets) writes
  *     grad_offsets[b] = grad_loss[b] * grad_unit[b], 8 floats per patch).
- * Errors: B < 0, h or w outside [2, 32768], h w > 2^29, NULL pointer with B > 0 ->
- * HG_EINVAL; B == 0 is a no-op.                                            */
+ * Errors: B outside [0, 2^27], h or w outside [2, 32768], h w > 2^29, NULL
+ * pointer with B > 0 -> HG_EINVAL; B == 0 is a no-op.                                            */
 int hg_photometric_fwd(const float *offsets, const float *img, const float *tgt, int32_t B,
                        int32_t h, int32_t w, float *loss, void *stream);
 int hg_photometric_bwd(const float *offsets, const float *img, const float *tgt,
@@ -364,9 +364,9 @@ int hg_scale_grad(const float *grad_unit, const float *grad_loss, int32_t B,
  * hg_refine launches on the stream; hg_refine_graph_create captures the same
  * sequence (with these pointers and scalars) for hg_graph_launch (allocates,
  * synchronises; needs B > 0).
- * Errors: B < 0, h or w outside [2, 32768], h w > 2^29, iters outside [0, 1000],
- * non-finite step, NULL img/tgt/offsets with B > 0 -> HG_EINVAL. B == 0 is a
- * no-op.                                                                   */
+ * Errors: B outside [0, 2^27], h or w outside [2, 32768], h w > 2^29, iters
+ * outside [0, 1000], non-finite step, NULL img/tgt/offsets with B > 0 ->
+ * HG_EINVAL. B == 0 is a no-op.                                                                   */
 int hg_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w, int32_t iters,
               float step, float *offsets, float *loss, void *stream);
 int hg_refine_graph_create(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,

@@ -695,8 +695,11 @@ __global__ void l1_bwd_kernel(const float *__restrict__ warped, const float *__r
   }
 }
 
+// Most patches per call (32-bit per-patch offsets such as 9 B stay in range).
+constexpr int32_t kMaxPatches = 1 << 27;
+
 static int check_img(const void *a, const void *b2, int B, int h, int w, const char *fn) {
-  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(B >= 0 && B <= kMaxPatches, "%s: B = %d outside [0, 2^27]", fn, B);
   HG_REQUIRE(h >= 1 && w >= 1 && h <= 32768 && w <= 32768 &&
                  static_cast<int64_t>(h) * w <= (int64_t(1) << 29),
              "%s: image size %d x %d out of range", fn, h, w);
@@ -707,19 +710,36 @@ static int check_img(const void *a, const void *b2, int B, int h, int w, const c
 
 // General quadrilaterals (the tensorised general ACA): src, dst B x 8 floats
 // (x_M y_M x_N y_N x_P y_P x_Q y_Q); H B x 9 doubles at ACA's own scale.
-__global__ void aca_fwd_kernel(const float *__restrict__ src, const float *__restrict__ dst,
-                               int B, double *__restrict__ H) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  double s[8], d[8], h[9];
+// One problem per thread, kDiffThreads per workgroup. The 9 doubles of each
+// H go through LDS, so that the workgroup's block of H (9 kDiffThreads
+// doubles, contiguous) is written as consecutive doubles: every store
+// instruction covers 512 contiguous bytes instead of lanes 72 bytes apart.
+__global__ __launch_bounds__(kDiffThreads) void aca_fwd_kernel(const float *__restrict__ src,
+                                                               const float *__restrict__ dst,
+                                                               int B, double *__restrict__ H) {
+  __shared__ double hs[9 * kDiffThreads];
+  const int b0 = blockIdx.x * kDiffThreads;
+  const int b = b0 + threadIdx.x;
+  if (b < B) {
+    double s[8], d[8], h[9];
+    const int64_t o = 8 * static_cast<int64_t>(b);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    s[k] = static_cast<double>(src[8 * b + k]);
-    d[k] = static_cast<double>(dst[8 * b + k]);
+    for (int k = 0; k < 8; ++k) {
+      s[k] = static_cast<double>(src[o + k]);
+      d[k] = static_cast<double>(dst[o + k]);
+    }
+    (void)aca_solve(s, d, h);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) hs[9 * threadIdx.x + i] = h[i];
   }
-  (void)aca_solve(s, d, h);
+  __syncthreads();
+  const int nd = 9 * min(kDiffThreads, B - b0);   // doubles of this workgroup's block
+  double *Hb = H + 9 * static_cast<int64_t>(b0);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) H[9 * b + i] = h[i];
+  for (int i = 0; i < 9; ++i) {
+    const int k = i * kDiffThreads + threadIdx.x;
+    if (k < nd) Hb[k] = hs[k];
+  }
 }
 
 __global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__restrict__ dst,
@@ -728,21 +748,22 @@ __global__ void aca_bwd_kernel(const float *__restrict__ src, const float *__res
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   double s[8], d[8], g[9], gs[8], gd[8];
+  const int64_t o = 8 * static_cast<int64_t>(b), oh = 9 * static_cast<int64_t>(b);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    s[k] = static_cast<double>(src[8 * b + k]);
-    d[k] = static_cast<double>(dst[8 * b + k]);
+    s[k] = static_cast<double>(src[o + k]);
+    d[k] = static_cast<double>(dst[o + k]);
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = gH[9 * b + i];
+  for (int i = 0; i < 9; ++i) g[i] = gH[oh + i];
   aca_vjp(s, d, g, gs, gd);
   if (gsrc) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) gsrc[8 * b + k] = static_cast<float>(gs[k]);
+    for (int k = 0; k < 8; ++k) gsrc[o + k] = static_cast<float>(gs[k]);
   }
   if (gdst) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) gdst[8 * b + k] = static_cast<float>(gd[k]);
+    for (int k = 0; k < 8; ++k) gdst[o + k] = static_cast<float>(gd[k]);
   }
 }
 
@@ -830,7 +851,7 @@ static int launch_refine(const RefineArgs &a, hipStream_t s) {
 static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h, int32_t w,
                        int32_t iters, float step, float *offsets, float *loss, const char *fn,
                        RefineArgs &a) {
-  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(B >= 0 && B <= kMaxPatches, "%s: B = %d outside [0, 2^27]", fn, B);
   HG_REQUIRE(h >= 2 && w >= 2 && h <= 32768 && w <= 32768 &&
                  static_cast<int64_t>(h) * w <= (int64_t(1) << 29),
              "%s: image size %d x %d out of range", fn, h, w);
@@ -850,7 +871,7 @@ static int make_refine(const float *img, const float *tgt, int32_t B, int32_t h,
 }
 
 static int check_rect(float w, float r, int B, const char *fn) {
-  HG_REQUIRE(B >= 0, "%s: B < 0", fn);
+  HG_REQUIRE(B >= 0 && B <= kMaxPatches, "%s: B = %d outside [0, 2^27]", fn, B);
   HG_REQUIRE(std::isfinite(w) && w > 0.0f && std::isfinite(r) && r > 0.0f,
              "%s: rectangle width and aspect ratio must be finite and > 0", fn);
   return HG_OK;
@@ -891,18 +912,18 @@ extern "C" int hg_aca_rect_bwd(const float *offsets, const double *grad_H, int32
 extern "C" int hg_aca_fwd(const float *src, const float *dst, int32_t B, double *H,
                           void *stream) {
   clear_error();
-  HG_REQUIRE(B >= 0, "hg_aca_fwd: B < 0");
+  HG_REQUIRE(B >= 0 && B <= (1 << 30), "hg_aca_fwd: B = %d outside [0, 2^30]", B);
   if (B == 0) return HG_OK;
   HG_REQUIRE(src && dst && H, "hg_aca_fwd: NULL pointer");
-  hipLaunchKernelGGL(aca_fwd_kernel, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream), src,
-                     dst, B, H);
+  hipLaunchKernelGGL(aca_fwd_kernel, dim3((B + kDiffThreads - 1) / kDiffThreads), dim3(kDiffThreads),
+                     0, as_stream(stream), src, dst, B, H);
   return launched("aca_fwd_kernel");
 }
 
 extern "C" int hg_aca_bwd(const float *src, const float *dst, const double *grad_H, int32_t B,
                           float *grad_src, float *grad_dst, void *stream) {
   clear_error();
-  HG_REQUIRE(B >= 0, "hg_aca_bwd: B < 0");
+  HG_REQUIRE(B >= 0 && B <= (1 << 30), "hg_aca_bwd: B = %d outside [0, 2^30]", B);
   if (B == 0) return HG_OK;
   HG_REQUIRE(src && dst && grad_H, "hg_aca_bwd: NULL src, dst or grad_H");
   HG_REQUIRE(grad_src || grad_dst, "hg_aca_bwd: both gradient outputs are NULL");

@@ -100,6 +100,10 @@ def test_general_aca_validation(lib):
     assert lib.hg_aca_bwd(FAKE, FAKE, FAKE, 4, None, None, None) == _abi.HG_EINVAL
     assert b"NULL" in lib.hg_last_error()
     assert lib.hg_aca_bwd(None, None, None, 0, None, None, None) == _abi.HG_OK
+    # batch limits (one thread per problem, 64-bit offsets): at most 2^30 problems
+    assert lib.hg_aca_fwd(FAKE, FAKE, (1 << 30) + 1, FAKE, None) == _abi.HG_EINVAL
+    assert lib.hg_aca_bwd(FAKE, FAKE, FAKE, (1 << 30) + 1, FAKE, FAKE, None) == _abi.HG_EINVAL
+    assert b"2^30" in lib.hg_last_error()
 
 
 def test_refine_and_photometric_validation(lib):
@@ -130,6 +134,13 @@ def test_refine_and_photometric_validation(lib):
     assert pb(FAKE, FAKE, FAKE, None, 4, 32, 32, FAKE, None) == _abi.HG_EINVAL
     assert pb(FAKE, FAKE, FAKE, FAKE, 4, 32, 32, None, None) == _abi.HG_EINVAL
     assert pf(None, None, None, 0, 32, 32, None, None) == _abi.HG_OK
+    # at most 2^27 patches per call (per-patch offsets stay 32-bit)
+    big = (1 << 27) + 1
+    assert pf(FAKE, FAKE, FAKE, big, 2, 2, FAKE, None) == _abi.HG_EINVAL
+    assert b"2^27" in lib.hg_last_error()
+    assert pb(FAKE, FAKE, FAKE, FAKE, big, 2, 2, FAKE, None) == _abi.HG_EINVAL
+    assert call(B=big, h=2, w=2) == _abi.HG_EINVAL
+    assert lib.hg_aca_rect_fwd(FAKE, big, 0.0, 0.0, 128.0, 1.0, FAKE, None) == _abi.HG_EINVAL
 
 
 def test_ransac_validation(lib):

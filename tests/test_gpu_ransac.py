@@ -124,6 +124,30 @@ def test_sizes(n, n_hyp, ld):
     check_pair(cs.corr, n_hyp, 77, f, label=f"n={n}")
 
 
+def test_fused_matches_plain_over_sizes():
+    """The fused form (8 waves per workgroup, hypotheses per workgroup chosen
+    from the count) and the plain form (4 waves per workgroup) give identical
+    outputs over pair sizes around every chunk boundary of either geometry and
+    hypothesis counts that select every workgroup shape (both are the float64
+    test's counts, so any difference is a geometry or tail error)."""
+    require_gpu()
+    rng = np.random.default_rng(20250)
+    sizes = [4, 63, 64, 65, 511, 512, 513, 1023, 2047, 2049, 4095, 4096, 4097, 6000, 8191, 8193,
+             12289, 20000]
+    hyps = [1, 5, 63, 64, 1000, 2049, 4096, 9000, 16384, 40000]
+    cases = [(int(n), int(rng.choice(hyps))) for n in sizes] + \
+            [(int(rng.integers(4, 20000)), int(rng.integers(1, 40000))) for _ in range(6)]
+    for k, (n, n_hyp) in enumerate(cases):
+        cs = synth.correspondences(n, float(rng.uniform(0.2, 0.8)), 3000 + k)
+        seed = int(rng.integers(0, 2**63))
+        announce(f"ransac fused vs plain n={n} hyps={n_hyp} seed={seed}")
+        f = run_single(cs.corr, n_hyp, seed)
+        p = run_single(cs.corr, n_hyp, seed, plain=True)
+        for key in f:
+            assert np.array_equal(f[key], p[key]), (n, n_hyp, key)
+        assert int(f["mask"].sum()) == int(f["best_count"][0]), (n, n_hyp)
+
+
 def test_all_degenerate_and_nonfinite():
     require_gpu()
     corr = np.ones((4, 50), np.float32)

@@ -187,6 +187,47 @@ def test_one_pixel_wide_images():
             assert torch.equal(Wp.cpu(), img.cpu())
 
 
+def test_warp_and_gradient_over_image_shapes():
+    """Random perspective maps that move parts of the patch outside the image,
+    over image shapes from 1 x 1 up: widths that divide the workgroup (each
+    thread walks one column) and that do not, widths wider than a workgroup,
+    one-pixel rows and columns. The stored warp equals the oracle's warp, and on
+    every shape the L1 loss and its gradient with respect to H match float64
+    autograd through the oracle's warp."""
+    require_gpu()
+    import paper_2402_18008_amd as hgpu
+    rng = np.random.default_rng(73)
+    shapes = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (16, 16), (17, 33), (64, 3), (5, 300),
+              (40, 257), (33, 64), (128, 128), (9, 512), (300, 2)]
+    for h, w in shapes:
+        B = 3
+        img = torch.from_numpy(rng.normal(size=(B, h, w)).astype(np.float32))
+        tgt = torch.from_numpy(rng.normal(size=(B, h, w)).astype(np.float32))
+        Hd = torch.zeros(B, 3, 3, dtype=torch.float64)
+        for b in range(B):
+            s_ = max(h, w)
+            Hd[b] = torch.tensor([[1 + 0.1 * rng.uniform(-1, 1), 0.1 * rng.uniform(-1, 1),
+                                   w * rng.uniform(-0.4, 0.4)],
+                                  [0.1 * rng.uniform(-1, 1), 1 + 0.1 * rng.uniform(-1, 1),
+                                   h * rng.uniform(-0.4, 0.4)],
+                                  [rng.uniform(-1, 1) * 0.02 / s_, rng.uniform(-1, 1) * 0.02 / s_, 1.0]],
+                                 dtype=torch.float64)
+        announce(f"warp and L1 gradient {h}x{w}")
+        Hc = Hd.reshape(B, 9).cuda()
+        Wp = hgpu.hg_warp_store_fwd(Hc, img.cuda())
+        L = hgpu.hg_warp_l1_fwd(Hc, img.cuda(), tgt.cuda())
+        gH = hgpu.hg_warp_l1_bwd(Hc, img.cuda(), tgt.cuda(), torch.ones(B, device="cuda"))
+        torch.cuda.synchronize()
+        Wr = ow.warp(img.double(), Hd)
+        assert (Wr - Wp.double().cpu()).abs().max() < 4e-6, (h, w)
+        Hr = Hd.clone().requires_grad_(True)
+        Lr = (ow.warp(img.double(), Hr) - tgt.double()).abs().mean(dim=(1, 2))
+        (gr,) = torch.autograd.grad(Lr.sum(), Hr)
+        assert np.allclose(L.cpu().numpy(), Lr.detach().numpy(), rtol=1e-5, atol=1e-7), (h, w)
+        eg = rel(gH.cpu().numpy().reshape(B, 9), gr.numpy().reshape(B, 9))
+        assert eg.max() < GRAD_TOL, (h, w, eg.max())
+
+
 def test_batch_of_several_rounds():
     """4096 patches of 64 x 64: about four rounds of resident workgroups (the
     per-wave priority schedule restarts in each); the single pass, the two

@@ -360,9 +360,9 @@ __global__ __launch_bounds__(kRefitThreads) void refit_kernel(
   const int64_t a = min(max(off[p], int64_t(0)), ld);
   const int64_t b = min(max(off[p + 1], a), ld);
   const float *X1 = corr, *Y1 = corr + ld, *X2 = corr + 2 * ld, *Y2 = corr + 3 * ld;
-  // reference point: the pair's first point, selected or not (any point of
-  // the pair keeps the shift's cancellation small); a coordinate that is not
-  // finite there is replaced by 0, so that unselected points never enter the sums
+  // reference point: the pair's first point, selected or not; a coordinate
+  // that is not finite there is replaced by 0, so that unselected points never
+  // enter the sums
   double rx = 0.0, ry = 0.0, ru = 0.0, rv = 0.0;
   if (b > a) {
     rx = static_cast<double>(X1[a]);
@@ -374,30 +374,63 @@ __global__ __launch_bounds__(kRefitThreads) void refit_kernel(
     ru = isfinite(ru) ? ru : 0.0;
     rv = isfinite(rv) ? rv : 0.0;
   }
+  // the count and the 29 moments of the selected points about the reference
+  // (workgroup sum in thread 0)
   double r[kRaw];
+  auto moments = [&]() {
 #pragma unroll
-  for (int k = 0; k < kRaw; ++k) r[k] = 0.0;
-  for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
-    PointBatch pb;
-    load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
+    for (int k = 0; k < kRaw; ++k) r[k] = 0.0;
+    for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += kRefitThreads * kBatch) {
+      PointBatch pb;
+      load_batch(X1, Y1, X2, Y2, mask, i0, b, pb);
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      if (!pb.sel[j]) continue;
-      const double x = static_cast<double>(pb.x1[j]) - rx, y = static_cast<double>(pb.y1[j]) - ry;
-      const double u = static_cast<double>(pb.x2[j]) - ru, v = static_cast<double>(pb.y2[j]) - rv;
-      const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
-      const double uu = u * u, vv = v * v;
+      for (int j = 0; j < kBatch; ++j) {
+        if (!pb.sel[j]) continue;
+        const double x = static_cast<double>(pb.x1[j]) - rx, y = static_cast<double>(pb.y1[j]) - ry;
+        const double u = static_cast<double>(pb.x2[j]) - ru, v = static_cast<double>(pb.y2[j]) - rv;
+        const double mono[6] = {x * x, x * y, x, y * y, y, 1.0};
+        const double uu = u * u, vv = v * v;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        r[k] += mono[k];
-        r[6 + k] += u * mono[k];
-        r[12 + k] += uu * mono[k];
-        r[18 + k] += v * mono[k];
-        r[24 + k] += vv * mono[k];
+        for (int k = 0; k < 6; ++k) {
+          r[k] += mono[k];
+          r[6 + k] += u * mono[k];
+          r[12 + k] += uu * mono[k];
+          r[18 + k] += v * mono[k];
+          r[24 + k] += vv * mono[k];
+        }
       }
     }
+    refit_block_sum(r);
+  };
+  moments();
+  // The shift to the centroids cancels about (distance / spread)^4 of the
+  // fourth moments: a reference more than 4 RMS spreads from the centroid of
+  // either side (an unselected outlier far from the rest) is replaced by the
+  // centroid found, and the moments are summed again about it.
+  __shared__ double again[5];
+  if (threadIdx.x == 0) {
+    const double n0 = r[5];
+    bool far = false;
+    if (n0 >= 4.0) {
+      const double ma = r[2] / n0, mb = r[4] / n0, mc = r[11] / n0, md = r[23] / n0;
+      const double s1 = (r[0] + r[3]) / n0 - (ma * ma + mb * mb);
+      const double s2 = (r[17] + r[29]) / n0 - (mc * mc + md * md);
+      far = !(ma * ma + mb * mb <= 16.0 * s1) || !(mc * mc + md * md <= 16.0 * s2);
+      again[1] = rx + ma;
+      again[2] = ry + mb;
+      again[3] = ru + mc;
+      again[4] = rv + md;
+    }
+    again[0] = far ? 1.0 : 0.0;
   }
-  refit_block_sum(r);
+  __syncthreads();
+  if (again[0] != 0.0) {   // uniform across the workgroup
+    rx = again[1];
+    ry = again[2];
+    ru = again[3];
+    rv = again[4];
+    moments();
+  }
   if (threadIdx.x != 0) return;
   const double n = r[5];
   const int used = static_cast<int>(n);

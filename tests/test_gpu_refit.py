@@ -91,6 +91,27 @@ def test_refit_masks_small_sets_and_no_mask():
     check(b.corr, b.off, None, Hg, ug, fg, label="all")
 
 
+def test_refit_reference_point_far_or_not_finite():
+    """The kernel sums moments about each pair's first point, selected or not.
+    An unselected first point far from the others (1e5 px away), or with
+    non-finite coordinates, changes nothing: the result matches the oracle on
+    the selected points."""
+    require_gpu()
+    b = synth.correspondence_batch(8, 43, n_min=200, n_max=600)
+    corr = b.corr.copy()
+    mask = b.inlier.astype(np.uint8)
+    for p in range(8):
+        a = int(b.off[p])
+        mask[a] = 0
+        if p % 2 == 0:
+            corr[:, a] = np.float32(1e5)                   # far away
+        else:
+            corr[:, a] = [np.nan, np.inf, -np.inf, np.nan]  # not finite
+    announce("refit_ho unselected first points far away / not finite")
+    Hg, ug, fg = gpu_refit(corr, b.off, mask)
+    check(corr, b.off, mask, Hg, ug, fg, label="reference point")
+
+
 def test_refit_exact_points():
     """Noise-free correspondences (rounded to float) give back the generating
     homography."""

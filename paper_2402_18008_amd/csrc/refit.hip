@@ -19,7 +19,9 @@
 // close for that to converge), recovers h1, h2,
 // denormalises and writes the power-of-two scaled float H. Moments about a
 // point of the pair rather than the origin keep the shift's cancellation to
-// the ratio of the pair's extent to its spread.
+// the ratio of that point's distance from the centroid to the spread; when the
+// point lies more than 4 RMS spreads away (an unselected outlier), the
+// moments are summed again about the centroid found.
 #include <cmath>
 
 #include "common.hpp"

@@ -19,7 +19,9 @@ Modules
               torch float64 (autograd through DLT) plus finite differences
 
 Every function is pinned by a ``-m "not gpu"`` test against exact arithmetic,
-invariants, special cases or a library routine; the one exception (the sampler
-stream itself, beyond published Philox known-answer vectors) is marked
-"parity unpinned" in its docstring.
+invariants, special cases, brute force or a library routine. The sampler's
+mapping from Philox words to point indices is this implementation's own
+choice: it is pinned by the published Philox known-answer vectors, brute force
+over every Floyd outcome for small N, and distinctness and uniformity, and has
+no external reference beyond those.
 """

@@ -1,8 +1,8 @@
 // RANSAC hypothesise-and-verify on the GPU.
 //
-// Work item = (pair, block of HB hypotheses). A 256-thread workgroup solves
-// its HB hypotheses (one per thread) into LDS, then scores them against the
-// pair's points: each lane holds P correspondences in registers, every lane
+// Work item = (pair, block of HB hypotheses). A workgroup (256 threads; 512
+// for the fused single pair) solves its HB hypotheses (one per thread) into
+// LDS, then scores them against the pair's points: each lane holds P correspondences in registers, every lane
 // reads the hypothesis from LDS, the inlier test runs per (hypothesis, point)
 // and counts come from a wavefront ballot + popcount. The argmax is over a
 // packed (count, ~index) key.
